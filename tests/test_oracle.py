@@ -1,0 +1,264 @@
+"""Pins of the CPU oracle against what the mathematics fixes (no GPU).
+
+Each test would fail for a plausible mistake somewhere in the oracle: a dropped
+Ewald term, a wrong sign or factor in G^N or Ghat^F, a wrong self term, a wrong
+reciprocal lattice, an index slip in the spectral stages.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import spectral as S
+from paper_2606_19059_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- classical Ewald
+
+
+@pytest.mark.parametrize("box", [(1.0, 1.0, 1.0), (1.0, 1.0, 2.0), (0.7, 1.3, 1.1)])
+def test_split_parameter_independence(box):
+    """G^N + G^F = G, so the Ewald total cannot depend on xi (Sec. 2).
+
+    A wrong relative factor between the real-space, Fourier and self terms, or a
+    wrong exponent in either screening function, breaks this.
+    """
+    L = np.array(box)
+    x, f = W.particles(7, L, seed=11)
+    ref = oracle.ewald_sum(x, f, L, xi=6.0 / min(box))
+    scale = np.max(np.abs(ref))
+    for xi in (3.5 / min(box), 9.0 / min(box), 12.0 / min(box)):
+        u = oracle.ewald_sum(x, f, L, xi=xi)
+        # the self term 4 xi/sqrt(pi) |f| exceeds |u| several-fold: allow its rounding
+        assert np.max(np.abs(u - ref)) / scale < 3e-12
+
+
+def test_split_parameter_independence_with_net_force():
+    """Also with sum f != 0 (the k = 0 mode is dropped on every side)."""
+    L = np.array([1.0, 1.0, 1.0])
+    rng = np.random.default_rng(5)
+    x = rng.random((3, 5))
+    f = rng.standard_normal((3, 5)) + 0.7
+    a = oracle.ewald_sum(x, f, L, xi=5.0)
+    b = oracle.ewald_sum(x, f, L, xi=10.0)
+    assert np.max(np.abs(a - b)) / np.max(np.abs(a)) < 1e-12
+
+
+def test_hasimoto_single_stokeslet_constant():
+    """N = 1 in a cube: u = -(4/3) K f / L with Hasimoto's lattice constant K."""
+    g = json.load(open(os.path.join(GOLDEN, "hasimoto_cubic.json")))
+    expected = -g["K"] * g["units_factor"]
+    for Lside in (1.0, 2.5):
+        L = np.array([Lside] * 3)
+        x = np.array([[0.31], [0.17], [0.74]]) * Lside
+        for fvec in ([1.0, 0.0, 0.0], [0.2, -0.5, 0.9]):
+            f = np.array(fvec).reshape(3, 1)
+            u = oracle.ewald_sum(x, f, L)
+            assert np.allclose(u[:, 0], expected * f[:, 0] / Lside, rtol=1e-10, atol=1e-12)
+
+
+def _surface_term(x, f, V):
+    """Spherical-summation limit minus Ewald value, for zero net force.
+
+    Derived from the k -> 0 behaviour of Ghat(k) S(k) e^{ik.x}: the O(1) term
+    8 pi (I - kk) sum_j f_j [(k.x)(k.x_j) - (k.x_j)^2/2] (unit k) averaged over
+    directions (<k_a k_b> = delta/3, <k_a k_b k_c k_d> = sym/15), divided by V.
+    """
+    n = x.shape[1]
+    out = np.zeros_like(x)
+    for i in range(n):
+        xi_ = x[:, i]
+        s = np.zeros(3)
+        for j in range(n):
+            xj, fj = x[:, j], f[:, j]
+            s += (4 / 15) * fj * (xi_ @ xj) - (1 / 15) * (xi_ * (fj @ xj) + xj * (fj @ xi_))
+            s += -(2 / 15) * fj * (xj @ xj) + (1 / 15) * xj * (fj @ xj)
+        out[:, i] = 8 * math.pi / V * s
+    return out
+
+
+def test_brute_force_spherical_image_sums():
+    """Plain image sums of G over growing spheres converge to the Ewald value.
+
+    (i) after removing the best affine field c + A x_i the residual falls like R^-3;
+    (ii) after removing the closed-form surface term the residual falls towards 0.
+    """
+    L = np.array([1.0, 1.0, 1.0])
+    x, f = W.particles(9, L, seed=7)
+    ue = oracle.ewald_sum(x, f, L)
+    du = _surface_term(x, f, 1.0)
+    X = np.hstack([np.ones((x.shape[1], 1)), x.T])
+    fit_res, cf_res = [], []
+    for R in (10.0, 20.0, 40.0):
+        d = oracle.direct_sphere(x, f, L, R) - ue
+        r = 0.0
+        for c in range(3):
+            coef, *_ = np.linalg.lstsq(X, d[c], rcond=None)
+            r = max(r, float(np.max(np.abs(d[c] - X @ coef))))
+        fit_res.append(r)
+        cf_res.append(float(np.max(np.abs(d - du))))
+    scale = np.max(np.abs(ue))
+    assert fit_res[0] > fit_res[1] > fit_res[2]
+    assert fit_res[2] / scale < 1e-6
+    assert fit_res[0] / fit_res[1] > 5.0  # ~R^-3
+    assert cf_res[0] > cf_res[2]
+    assert cf_res[2] / scale < 1e-3
+    # the surface term itself is O(1): without it the sums are far from the Ewald value
+    assert np.max(np.abs(du)) / scale > 0.05
+
+
+def test_mobility_matrix_symmetry():
+    """G_per is even and symmetric: g . u(f) = f . u(g)."""
+    L = np.array([1.0, 1.0, 2.0])
+    rng = np.random.default_rng(3)
+    x = rng.random((3, 12)) * L.reshape(3, 1)
+    f = rng.standard_normal((3, 12))
+    g = rng.standard_normal((3, 12))
+    a = float(np.sum(g * oracle.ewald_sum(x, f, L)))
+    b = float(np.sum(f * oracle.ewald_sum(x, g, L)))
+    assert abs(a - b) <= 1e-12 * max(abs(a), 1.0)
+
+
+def test_linearity_translation_permutation():
+    L = np.array([1.0, 1.0, 1.0])
+    x, f = W.particles(20, L, seed=9)
+    _, g = W.particles(20, L, seed=10)
+    u = oracle.ewald_sum(x, f, L)
+    assert np.allclose(oracle.ewald_sum(x, 2.0 * f - 0.5 * g, L),
+                       2.0 * u - 0.5 * oracle.ewald_sum(x, g, L), rtol=0, atol=1e-12 * np.max(np.abs(u)))
+    assert np.all(oracle.ewald_sum(x, np.zeros_like(f), L) == 0.0)
+    shift = np.array([[0.3], [-0.77], [1.6]])
+    ut = oracle.ewald_sum(x + shift, f, L)
+    assert np.max(np.abs(ut - u)) < 1e-12 * np.max(np.abs(u))
+    p = np.random.default_rng(0).permutation(20)
+    up = oracle.ewald_sum(x[:, p], f[:, p], L)
+    assert np.max(np.abs(up - u[:, p])) < 1e-12 * np.max(np.abs(u))
+
+
+def test_sampled_targets_match_full():
+    L = np.array([1.0, 1.0, 1.0])
+    x, f = W.particles(300, L, seed=12)
+    u = oracle.ewald_sum(x, f, L)
+    t = W.sample_targets(300, 17, seed=1)
+    ut = oracle.ewald_sum(x, f, L, targets=t)
+    assert np.max(np.abs(ut - u[:, t])) < 1e-12 * np.max(np.abs(u))
+
+
+def test_real_space_reduces_to_stokeslet_for_tiny_xi():
+    """As xi -> 0 the screened kernel G^N tends to the plain Stokeslet G (eq. g-near)."""
+    L = np.array([1.0, 1.0, 1.0])
+    x, f = W.particles(6, L, seed=2)
+    rc = 0.45
+    ur = oracle.real_space(x, f, L, 1e-7, rc)
+    ref = np.zeros_like(ur)
+    xw = oracle.wrap(x, L)
+    for i in range(6):
+        for j in range(6):
+            for m in np.ndindex(3, 3, 3):
+                r = xw[:, i] - xw[:, j] + (np.array(m) - 1.0)
+                d = np.linalg.norm(r)
+                if 0 < d < rc:
+                    ref[:, i] += f[:, j] / d + r * (r @ f[:, j]) / d**3
+    assert np.max(np.abs(ur - ref)) < 1e-6 * np.max(np.abs(ref))
+
+
+def test_real_space_cutoff_saturates():
+    """Beyond ~6/xi the real-space term no longer changes (erfc tail)."""
+    L = np.array([1.0, 1.0, 1.0])
+    x, f = W.particles(40, L, seed=4)
+    a = oracle.real_space(x, f, L, 12.0, 0.5)
+    b = oracle.real_space(x, f, L, 12.0, 0.8)
+    assert np.max(np.abs(a - b)) < 1e-14 * np.max(np.abs(a))
+
+
+# ---------------------------------------------------------------- spectral stages
+
+
+def test_p2g_single_point_on_grid_node():
+    """A unit force exactly on a grid node spreads the separable Gaussian e^{-beta j^2}."""
+    L = (1.0, 1.0, 1.0)
+    M = (16, 16, 16)
+    P, m = 8, 4.5
+    x = np.array([[5.0 / 16], [0.0], [9.0 / 16]])
+    f = np.array([[1.0], [0.0], [0.0]])
+    phi = S.p2g(x, f, L, M, P, m)
+    beta = 2 * m * m / P**2
+    offs = np.arange(-(P // 2 - 1), P // 2 + 1)
+    w = np.exp(-beta * offs.astype(float) ** 2)
+    # the node at offset +P/2 lies exactly at distance P h / 2: outside the open support
+    w[offs == P // 2] = 0.0
+    expect = np.zeros(M)
+    for a, wa in zip(offs, w):
+        for b, wb in zip(offs, w):
+            for c, wc in zip(offs, w):
+                expect[(5 + a) % 16, b % 16, (9 + c) % 16] = wa * wb * wc
+    assert np.allclose(phi[0], expect, rtol=0, atol=1e-15)
+    assert np.all(phi[1] == 0) and np.all(phi[2] == 0)
+
+
+def test_p2g_translation_by_grid_cells_is_a_roll():
+    L = (1.0, 1.0, 1.0)
+    M = (12, 16, 8)
+    x, f = W.particles(30, L, seed=21)
+    phi = S.p2g(x, f, L, M, 6, 4.0)
+    sh = np.array([[3.0 / 12], [-5.0 / 16], [1.0 / 8]])
+    phi2 = S.p2g(x + sh, f, L, M, 6, 4.0)
+    assert np.allclose(np.roll(phi, (3, -5, 1), axis=(1, 2, 3)), phi2, rtol=0, atol=1e-13)
+
+
+def test_g2p_is_h3_times_p2g_transpose():
+    """<g, G2P(v)> = h^3 <P2G(g), v>: interpolation is the adjoint of spreading (eq. p2g, g2p)."""
+    L = (1.0, 1.2, 0.9)
+    M = (10, 12, 8)
+    x, g = W.particles(25, L, seed=31)
+    rng = np.random.default_rng(1)
+    v = rng.standard_normal((3,) + M)
+    h3 = (L[0] / M[0]) * (L[1] / M[1]) * (L[2] / M[2])
+    lhs = np.sum(g * S.g2p(v, x, L, M, 6, 4.2))
+    rhs = h3 * np.sum(S.p2g(x, g, L, M, 6, 4.2) * v)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_far_field_converges_to_fourier_sum():
+    """P2G -> FFT -> CNV -> IFFT -> G2P approximates the direct Fourier sum (same xi).
+
+    The error falls with the window support P and matches the window-error
+    model within a small factor; a wrong deconvolution, Ghat^F factor or grid
+    normalisation would leave an O(1) error.
+    """
+    L = np.array([1.0, 1.0, 1.0])
+    x, f = W.particles(200, L, seed=1)
+    xi = 11.444
+    ref = oracle.recip_space(x, f, L, xi, 12 * 60)
+    errs = []
+    for P in (6, 8, 10):
+        m = 0.94 * math.sqrt(math.pi * P)
+        uf = S.far_field(x, f, L, (32, 32, 32), xi, P, m)
+        errs.append(oracle.rel_err(uf, ref))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[1] < 6e-5 and errs[2] < 6e-6
+
+
+def test_far_field_anisotropic_box():
+    L = np.array([1.0, 1.0, 2.0])
+    x, f = W.particles(150, L, seed=8)
+    xi = 11.0
+    ref = oracle.recip_space(x, f, L, xi, 12 * 60)
+    uf = S.far_field(x, f, L, (32, 32, 64), xi, 10, 0.94 * math.sqrt(10 * math.pi))
+    assert oracle.rel_err(uf, ref) < 6e-6
+
+
+def test_spectral_total_matches_classical_ewald():
+    """Algorithm se (P2P + far field + self) against the plain definition."""
+    L = np.array([1.0, 1.0, 1.0])
+    x, f = W.particles(400, L, seed=1)
+    ue = oracle.ewald_sum(x, f, L)
+    xi, rc = 10.282, 0.4798
+    P = 12
+    u = S.spectral_ewald(x, f, L, (32, 32, 32), xi, rc, P, 0.94 * math.sqrt(math.pi * P))
+    assert oracle.rel_err(u, ue) < 3e-7
