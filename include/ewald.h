@@ -1,0 +1,177 @@
+/*
+ * ewald.h -- C ABI of the MI355X spectral Ewald library for the triply
+ * periodic Stokeslet sum.
+ *
+ * The library evaluates, for N particles x_i in an orthorhombic periodic box
+ * B = [0,L1) x [0,L2) x [0,L3) with forces f_i,
+ *
+ *     u(x_i) = sum_j sum_p' G(x_i - x_j + p) f_j,   G(r) = I/|r| + r r^T/|r|^3,
+ *
+ * (Sec. 2, eq. (potentials) and the Stokeslet below it; targets = sources;
+ * coincident points skipped; no 1/(8 pi mu) factor), with Hasimoto's Ewald
+ * split into a near field (P2P, Sec. 2.1 eq. (g-near)) and a far field
+ * evaluated on a uniform grid (P2G, FFT, CNV, IFFT, G2P: Sec. 2.2, eq. (p2g),
+ * (sca), (g2p), with Ghat^F of eq. (GFk)), plus the self-term correction
+ * -(4 xi / sqrt(pi)) f_i.  The k = 0 Fourier mode is dropped (Hasimoto's
+ * convention: a net force is balanced by a mean pressure gradient).
+ *
+ * Conventions shared by every entry point:
+ *  - Arrays x, f, u are structure-of-arrays (3, n) FP64 in DEVICE memory:
+ *    component d of particle i is at [d*n + i].  They are owned by the caller.
+ *  - `workspace` is caller-owned device memory of at least
+ *    ewald_workspace_bytes(plan, n) bytes, 256-byte aligned.  A plan owns only
+ *    small read-only tables, so one plan can serve concurrent evaluations on
+ *    different streams as long as each uses its own workspace.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Evaluation entry
+ *    points only enqueue work on it: they allocate nothing, do not
+ *    synchronise, and return before the device has finished.  Device faults
+ *    surface at the caller's next synchronisation.
+ *  - Return values: EWALD_OK (0) or a negative ewald_status; the message of
+ *    the last failure on the calling thread is returned by ewald_last_error().
+ *    All argument checks happen before anything is enqueued.  The library
+ *    never aborts or prints.
+ *  - Positions outside [0, L) are wrapped periodically.  n = 0 is a no-op.
+ */
+#ifndef EWALD_H
+#define EWALD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ewald_plan_s* ewald_plan_t;
+
+typedef enum {
+    EWALD_OK = 0,
+    EWALD_EINVAL = -1,       /* bad argument, size or parameter */
+    EWALD_ENOMEM = -2,       /* workspace too small, or a plan table allocation failed */
+    EWALD_EHIP = -3,         /* a HIP runtime call failed */
+    EWALD_EUNSUPPORTED = -4  /* valid request outside what this build implements */
+} ewald_status;
+
+/* Precision modes (low byte of ewald_params.precision) and flags (OR'd in). */
+enum {
+    EWALD_FP64 = 0,      /* every step in FP64 */
+    EWALD_FP32_BULK = 1, /* P2P, P2G, FFT, G2P in FP32; Fourier-space scaling, k = 0 and
+                            self terms, final sum in FP64 */
+    EWALD_FLAG_P2P_FP64_ACC = 1 << 8, /* FP32 bulk: accumulate each particle's near-field
+                                         sum in FP64 (automatic when tol < 1e-7) */
+    EWALD_FLAG_STAGE_TIMERS = 1 << 9  /* record per-stage HIP events (see ewald_stage_ms) */
+};
+
+/*
+ * Plan parameters.  Any parameter given as <= 0 is derived from `tol`
+ * following the error split of Sec. 2.3 (eq. (ese), each error term held to
+ * tol/3): xi from the grid spacing (E^F), r_c from xi (E^N), the window
+ * support P and shape from the Gaussian-window error model, the grid from
+ * r_c when neither grid nor xi is given.
+ */
+typedef struct {
+    double box[3];       /* L1, L2, L3 > 0: orthorhombic, triply periodic */
+    double xi;           /* Ewald split parameter; <= 0: derive */
+    double r_c;          /* near-field cutoff radius; <= 0: derive */
+    int32_t grid[3];     /* M1, M2, M3: powers of two in [8, 512]; any <= 0: derive */
+    int32_t P;           /* window support in grid points per dimension: even, 4..16; <= 0: derive */
+    double tol;          /* target relative RMS error, in [1e-12, 1e-2] */
+    int32_t precision;   /* EWALD_FP64 or EWALD_FP32_BULK, OR'd with EWALD_FLAG_* */
+    int32_t reserved;    /* must be 0 */
+    int64_t n_max;       /* largest n this plan will evaluate (sizes workspace queries) */
+    double window_shape; /* Gaussian shape m (w0(d) = exp(-2 m^2 d^2 / (P h)^2)); <= 0: derive */
+} ewald_params;
+
+/* Everything a plan resolved (returned by ewald_plan_get_info). */
+typedef struct {
+    ewald_params params;      /* every field resolved */
+    double h[3];              /* grid spacing L_d / M_d */
+    double err_near;          /* predicted near-field RMS error term E^N (eq. (ese)) */
+    double err_far;           /* predicted Fourier truncation term E^F (eq. (ese)) */
+    double err_window;        /* predicted window error (Gaussian-window model) */
+    int32_t tile;             /* P2P cell edge, in grid cells */
+    int32_t n_tiles[3];       /* P2P cells per dimension */
+    int32_t stencil[3];       /* P2P neighbour half-width, in cells */
+    int32_t reserved;
+    int64_t workspace_bytes;  /* ewald_workspace_bytes(plan, n_max) */
+} ewald_plan_info;
+
+/* Create a plan (host call; allocates the plan's small device tables on the
+ * current device).  Fails with EWALD_EINVAL for: box <= 0, tol outside its
+ * range, a grid entry that is not a power of two in [8, 512], odd P or P
+ * outside 4..16, r_c above the smallest box side or below one grid spacing,
+ * n_max < 0, a non-zero reserved field. */
+int ewald_plan_create(const ewald_params* params, ewald_plan_t* plan_out);
+
+/* Resolve parameters exactly as ewald_plan_create would, without creating a plan or
+ * touching the device (host only); fills *info, including workspace_bytes for n_max.
+ * Same validation errors as ewald_plan_create. */
+int ewald_resolve(const ewald_params* params, ewald_plan_info* info);
+
+/* Copy the resolved parameters of `plan` into *info. */
+int ewald_plan_get_info(ewald_plan_t plan, ewald_plan_info* info);
+
+/* Free the plan's tables and events.  No evaluation using it may be in flight. */
+int ewald_plan_destroy(ewald_plan_t plan);
+
+/* Workspace bytes ewald_eval needs for n particles (negative status on error). */
+int64_t ewald_workspace_bytes(ewald_plan_t plan, int64_t n);
+
+/*
+ * Full evaluation u = u^N + u^F - (4 xi/sqrt(pi)) f (Algorithm "se": P2P,
+ * P2G, FFT, CNV, IFFT, G2P, SUM).  x, f: (3, n) FP64 device inputs; u: (3, n)
+ * FP64 device output, fully overwritten.  Errors: EWALD_EINVAL for a null
+ * pointer with n > 0, n < 0 or n > n_max; EWALD_ENOMEM when workspace_bytes
+ * is below ewald_workspace_bytes(plan, n); EWALD_EHIP if a launch fails.
+ */
+int ewald_eval(ewald_plan_t plan, int64_t n, const double* x, const double* f, double* u,
+               void* workspace, int64_t workspace_bytes, void* stream);
+
+/*
+ * Diagnostic split of ewald_eval: u_near = the P2P sum (Sec. 2.1,
+ * eq. (potentials-near)) and u_far = the interpolated far field u^F_h
+ * (eq. (g2p)), both (3, n) FP64 device arrays in the caller's particle order,
+ * so that u = u_near + u_far - (4 xi/sqrt(pi)) f.  Same kernels, same
+ * arguments and errors as ewald_eval.
+ */
+int ewald_eval_parts(ewald_plan_t plan, int64_t n, const double* x, const double* f,
+                     double* u_near, double* u_far, void* workspace, int64_t workspace_bytes,
+                     void* stream);
+
+/*
+ * Diagnostic: the P2G grid phi (eq. (p2g), no h^3 factor) as (3, M1, M2, M3)
+ * row-major (M3 fastest), in the plan's grid precision (double for
+ * EWALD_FP64, float for EWALD_FP32_BULK).  `grid` is device memory of
+ * 3*M1*M2*M3 elements.
+ */
+int ewald_spread(ewald_plan_t plan, int64_t n, const double* x, const double* f, void* grid,
+                 void* workspace, int64_t workspace_bytes, void* stream);
+
+/*
+ * Diagnostic: the real grid that G2P interpolates, after P2G, FFT, CNV
+ * (eq. (sca)) and IFFT, stored as h1 h2 h3 * v(g_l) of eq. (g2p) (the h^3
+ * factor and the inverse-DFT normalisation are folded into CNV), layout and
+ * precision as for ewald_spread.
+ */
+int ewald_far_grid(ewald_plan_t plan, int64_t n, const double* x, const double* f, void* grid,
+                   void* workspace, int64_t workspace_bytes, void* stream);
+
+/*
+ * Per-stage device times (ms) of the last evaluation made with this plan when
+ * it was created with EWALD_FLAG_STAGE_TIMERS; valid once that evaluation's
+ * stream has been synchronised.  Stages, in order: 0 bin/sort, 1 P2P, 2 P2G,
+ * 3 FFT+CNV+IFFT, 4 G2P+self+sum+unsort, 5 total.  Writes min(count, 6)
+ * values; returns the number written or a negative status.
+ */
+int ewald_stage_ms(ewald_plan_t plan, float* ms, int32_t count);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* ewald_last_error(void);
+
+/* Library version string. */
+const char* ewald_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EWALD_H */

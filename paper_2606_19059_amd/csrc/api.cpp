@@ -1,0 +1,535 @@
+// C ABI of the spectral Ewald library: plan (parameter selection, tables), workspace
+// layout, and the stage sequence of Algorithm "se".
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace ewald {
+int p2g_max_runs();
+}
+
+using namespace ewald;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(EWALD_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(int v)
+{
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+int next_pow2(double v)
+{
+    int p = 1;
+    while (p < v) p *= 2;
+    return p;
+}
+
+// ---- error estimates, Sec. 2.3 eq. (ese) (unit box, unit force norm) ----
+
+double err_near(double xi, double rc)
+{
+    return std::sqrt(112.0 / 9.0 * std::pow(xi, 4) * rc * rc * rc) * std::exp(-xi * xi * rc * rc);
+}
+
+double err_far(double xi, double h)
+{
+    return 4.0 / (3.0 * h) * std::sqrt(3.5) * std::exp(-M_PI * M_PI / std::pow(2.0 * h * xi, 2));
+}
+
+// xi with E^F(xi, h) = target: pi^2 / (2 h xi)^2 = ln(4 sqrt(7/2) / (3 h target))
+double xi_from_grid(double h, double target)
+{
+    const double a = std::log(4.0 * std::sqrt(3.5) / (3.0 * h * target));
+    if (a <= 0.1) return M_PI / (2.0 * h * std::sqrt(0.1));
+    return M_PI / (2.0 * h * std::sqrt(a));
+}
+
+// h with E^F(xi, h) = target (E^F increases with h on the branch of interest): bisection
+double h_from_xi(double xi, double target)
+{
+    double lo = 1e-6 / xi, hi = 10.0 / xi;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = std::sqrt(lo * hi);
+        if (err_far(xi, mid) > target) hi = mid; else lo = mid;
+    }
+    return lo;
+}
+
+// r_c with E^N(xi, r_c) = target, on the decreasing branch r_c > 1/xi
+double rc_from_xi(double xi, double target)
+{
+    double lo = 1.0 / xi, hi = 40.0 / xi;
+    if (err_near(xi, lo) <= target) return lo;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (err_near(xi, mid) > target) lo = mid; else hi = mid;
+    }
+    return hi;
+}
+
+// xi with E^N(xi, r_c) = target for a given r_c (E^N decreases with xi for xi r_c > 1)
+double xi_from_rc(double rc, double target)
+{
+    double lo = 1.0 / rc, hi = 40.0 / rc;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (err_near(mid, rc) > target) lo = mid; else hi = mid;
+    }
+    return hi;
+}
+
+// Gaussian window error model (relative to the far field).  Truncating the Gaussian at
+// |d| = P h / 2 leaves e^{-m^2/2}; sampling it on the grid aliases the band k ~ 2 pi/h - k
+// onto k, attenuated by what(2 pi/h - k)/what(k) and weighted by Ghat^F(k) ~ e^{-k^2/(4 xi^2)};
+// the worst k gives exp(-(pi^2 P^2 / (2 m^2)) (1 - eta/2)), eta = (P h xi / m)^2.
+double err_window(int P, double m, double h, double xi)
+{
+    const double eta = std::pow(P * h * xi / m, 2);
+    const double alias = std::exp(-(M_PI * M_PI * P * P / (2.0 * m * m)) * std::max(0.0, 1.0 - 0.5 * eta));
+    return std::exp(-0.5 * m * m) + alias;
+}
+
+double best_shape(int P, double h, double xi)
+{
+    double best_m = std::sqrt(M_PI * P), best_e = 1e300;
+    for (double c = 0.6; c <= 1.4; c += 0.002) {
+        const double m = c * std::sqrt(M_PI * P);
+        const double e = err_window(P, m, h, xi);
+        if (e < best_e) {
+            best_e = e;
+            best_m = m;
+        }
+    }
+    return best_m;
+}
+
+int64_t align256(int64_t v) { return (v + 255) & ~(int64_t)255; }
+
+}  // namespace
+
+namespace ewald {
+
+int64_t layout_work(const Plan& pl, int64_t n, char* base, Work* w)
+{
+    const Geometry& g = pl.g;
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) -> char* {
+        char* p = base ? base + off : nullptr;
+        off += align256(bytes);
+        return p;
+    };
+    const int64_t nn = std::max<int64_t>(n, 1);
+    const size_t real = (pl.mode == EWALD_FP64) ? 8 : 4;
+    const size_t recsz = (pl.mode == EWALD_FP64) ? sizeof(Rec64) : sizeof(Rec32);
+    Work tmp;
+    Work* o = w ? w : &tmp;
+    o->key = (int*)take(4 * nn);
+    o->perm = (int*)take(4 * nn);
+    o->count = (int*)take(4 * (int64_t)g.ncells);
+    o->start = (int*)take(4 * ((int64_t)g.ncells + 1));
+    o->chunk_off = (int*)take(4 * ((int64_t)g.ntiles + 1));
+    o->part = (int*)take(4 * (int64_t)scan_part_elems(std::max(g.ncells, g.ntiles)));
+    o->rec = (void*)take((int64_t)recsz * nn);
+    o->u_near = (double*)take(8 * 3 * nn);
+    o->grid = (void*)take((int64_t)real * 3 * g.ncells);
+    o->bytes = off;
+    return off;
+}
+
+}  // namespace ewald
+
+namespace {
+
+int validate_and_resolve(const ewald_params* in, Plan* pl)
+{
+    ewald_params p = *in;
+    for (int d = 0; d < 3; ++d)
+        if (!(p.box[d] > 0.0) || !std::isfinite(p.box[d]))
+            return fail(EWALD_EINVAL, "box[%d] = %g must be positive and finite", d, p.box[d]);
+    if (!(p.tol >= 1e-12 && p.tol <= 1e-2))
+        return fail(EWALD_EINVAL, "tol = %g outside [1e-12, 1e-2]", p.tol);
+    if (p.reserved != 0) return fail(EWALD_EINVAL, "reserved field must be 0");
+    if (p.n_max < 0) return fail(EWALD_EINVAL, "n_max = %lld < 0", (long long)p.n_max);
+    if (p.n_max > (int64_t)1 << 30) return fail(EWALD_EUNSUPPORTED, "n_max above 2^30");
+    const int mode = p.precision & 0xff;
+    if (mode != EWALD_FP64 && mode != EWALD_FP32_BULK)
+        return fail(EWALD_EINVAL, "unknown precision mode %d", mode);
+    if (p.precision & ~(0xff | EWALD_FLAG_P2P_FP64_ACC | EWALD_FLAG_STAGE_TIMERS))
+        return fail(EWALD_EINVAL, "unknown precision flags 0x%x", p.precision);
+    if (mode == EWALD_FP32_BULK) return fail(EWALD_EUNSUPPORTED, "FP32 bulk mode is not built yet");
+    const bool grid_given = p.grid[0] > 0 && p.grid[1] > 0 && p.grid[2] > 0;
+    if (grid_given)
+        for (int d = 0; d < 3; ++d)
+            if (!is_pow2(p.grid[d]) || p.grid[d] < 8 || p.grid[d] > 512)
+                return fail(EWALD_EINVAL, "grid[%d] = %d must be a power of two in [8, 512]", d, p.grid[d]);
+    if (p.P > 0 && (p.P % 2 != 0 || p.P < 4 || p.P > 16))
+        return fail(EWALD_EINVAL, "P = %d must be even, in 4..16", p.P);
+    const double third = p.tol / 3.0;
+    const double Lmin = std::min(p.box[0], std::min(p.box[1], p.box[2]));
+
+    // grid and split parameter (E^F = tol/3), cutoff (E^N = tol/3)
+    double h = 0.0;
+    if (grid_given) {
+        for (int d = 0; d < 3; ++d) h = std::max(h, p.box[d] / p.grid[d]);
+        if (!(p.xi > 0)) p.xi = xi_from_grid(h, third);
+    } else {
+        const bool xi_given = p.xi > 0;
+        if (!(p.xi > 0)) {
+            double rc = p.r_c;
+            if (!(rc > 0)) {
+                // about 300 neighbours per particle at n_max (at least 2 grid-scale cells)
+                const double V = p.box[0] * p.box[1] * p.box[2];
+                const double nmax = std::max<double>(p.n_max, 1000.0);
+                rc = std::cbrt(300.0 * V / (nmax * 4.0 / 3.0 * M_PI));
+                rc = std::min(rc, 0.45 * Lmin);
+            }
+            p.xi = xi_from_rc(rc, third);
+        }
+        h = h_from_xi(p.xi, third);
+        for (int d = 0; d < 3; ++d) {
+            int M = next_pow2(p.box[d] / h);
+            M = std::max(8, std::min(512, M));
+            p.grid[d] = M;
+        }
+        h = 0.0;
+        for (int d = 0; d < 3; ++d) h = std::max(h, p.box[d] / p.grid[d]);
+        // the power-of-two grid is at least as fine as needed: unless xi was given, raise
+        // xi to what the grid resolves (E^F = tol/3), which shrinks r_c and the P2P work;
+        // a grid capped at 512 lowers xi instead
+        if (!xi_given) p.xi = xi_from_grid(h, third);
+        else p.xi = std::min(p.xi, xi_from_grid(h, third));
+    }
+    if (!(p.r_c > 0)) p.r_c = rc_from_xi(p.xi, third);
+    if (!(p.xi > 0) || !std::isfinite(p.xi)) return fail(EWALD_EINVAL, "xi = %g invalid", p.xi);
+    if (p.r_c > Lmin) return fail(EWALD_EINVAL, "r_c = %g exceeds the smallest box side %g", p.r_c, Lmin);
+    double hmin = 1e300;
+    for (int d = 0; d < 3; ++d) hmin = std::min(hmin, p.box[d] / p.grid[d]);
+    if (p.r_c < hmin) return fail(EWALD_EINVAL, "r_c = %g below the grid spacing %g", p.r_c, hmin);
+
+    // window support and shape
+    if (!(p.P > 0)) {
+        p.P = 16;
+        for (int P = 4; P <= 16; P += 2) {
+            const double m = best_shape(P, h, p.xi);
+            if (err_window(P, m, h, p.xi) <= third) {
+                p.P = P;
+                break;
+            }
+        }
+    }
+    if (!(p.window_shape > 0)) p.window_shape = best_shape(p.P, h, p.xi);
+
+    pl->p = p;
+    pl->mode = mode;
+    pl->fp64acc = (p.precision & EWALD_FLAG_P2P_FP64_ACC) || p.tol < 1e-7;
+    pl->timers = (p.precision & EWALD_FLAG_STAGE_TIMERS) != 0;
+    pl->P = p.P;
+    pl->m = p.window_shape;
+    pl->beta = 2.0 * p.window_shape * p.window_shape / ((double)p.P * p.P);
+    pl->xi = p.xi;
+    pl->rc = p.r_c;
+
+    Geometry& g = pl->g;
+    for (int d = 0; d < 3; ++d) {
+        g.L[d] = p.box[d];
+        g.M[d] = p.grid[d];
+        g.h[d] = p.box[d] / p.grid[d];
+    }
+    // P2P tile: edge ~ r_c / 2.5 grid cells, power of two in [2, 16], not above any M
+    int B = next_pow2(p.r_c / (2.5 * hmin) / std::sqrt(2.0));
+    B = std::max(2, std::min(16, B));
+    for (int d = 0; d < 3; ++d) B = std::min(B, g.M[d]);
+    g.B = B;
+    g.log2B = ilog2(B);
+    g.ncells = g.M[0] * g.M[1] * g.M[2];
+    g.ntiles = 1;
+    for (int d = 0; d < 3; ++d) {
+        g.NT[d] = g.M[d] / B;
+        g.S[d] = (int)std::ceil(p.r_c / (B * g.h[d]) - 1e-12);
+        g.ntiles *= g.NT[d];
+    }
+    // P2G run table bound: (8 + P - 1) window rows x z-tile segments
+    const int W = 8 + p.P - 1;
+    const int nzs = (W - 1) / B + 2;
+    if (W * nzs > p2g_max_runs())
+        return fail(EWALD_EUNSUPPORTED, "window P = %d with tile %d exceeds the P2G run table", p.P, B);
+
+    ewald_plan_info& info = pl->info;
+    std::memset(&info, 0, sizeof info);
+    info.params = p;
+    for (int d = 0; d < 3; ++d) {
+        info.h[d] = g.h[d];
+        info.n_tiles[d] = g.NT[d];
+        info.stencil[d] = g.S[d];
+    }
+    info.err_near = err_near(p.xi, p.r_c);
+    info.err_far = err_far(p.xi, h);
+    info.err_window = err_window(p.P, p.window_shape, h, p.xi);
+    info.tile = B;
+    info.workspace_bytes = layout_work(*pl, p.n_max, nullptr, nullptr);
+    return EWALD_OK;
+}
+
+int build_tables(Plan* pl)
+{
+    const Geometry& g = pl->g;
+    const int M1 = g.M[0], M2 = g.M[1], M3 = g.M[2], H = M3 / 2;
+    // CNV factors E_d[k] = (alpha_d/pi) exp(k_d^2 (1/(2 alpha_d) - 1/(4 xi^2))), Nyquist -> 0,
+    // with the scale h1 h2 h3 / (M1 M2 M3) folded into E_0
+    const int lens[3] = {M1, M2, H};
+    const double scale = (g.h[0] * g.h[1] * g.h[2]) / ((double)M1 * M2 * M3);
+    std::vector<double> cnv;
+    size_t cnv_off[3];
+    for (int d = 0; d < 3; ++d) {
+        cnv_off[d] = cnv.size();
+        const double alpha = 2.0 * pl->m * pl->m / std::pow(pl->P * g.h[d], 2);
+        for (int k = 0; k < lens[d]; ++k) {
+            int ks = k;
+            if (d < 2) ks = (k < g.M[d] / 2) ? k : k - g.M[d];
+            const bool nyq = (d < 2) && (k == g.M[d] / 2);
+            const double kk = std::pow(2.0 * M_PI * ks / g.L[d], 2);
+            double v = nyq ? 0.0 : (alpha / M_PI) * std::exp(kk * (1.0 / (2.0 * alpha) - 1.0 / (4.0 * pl->xi * pl->xi)));
+            if (d == 0) v *= scale;
+            cnv.push_back(v);
+        }
+    }
+    // twiddles e^{-2 pi i j / n} for n = M1, M2, M3/2, M3
+    const int tl[4] = {M1, M2, H, M3};
+    std::vector<double> tw64;
+    std::vector<float> tw32;
+    for (int a = 0; a < 4; ++a) {
+        pl->tw_off[a] = (int)(tw64.size() / 2);
+        for (int j = 0; j < tl[a]; ++j) {
+            // angle reduced to the first octant by symmetry for accuracy
+            const double ang = -2.0 * M_PI * (double)j / tl[a];
+            const double c = std::cos(ang), s = std::sin(ang);
+            tw64.push_back(c);
+            tw64.push_back(s);
+            tw32.push_back((float)c);
+            tw32.push_back((float)s);
+        }
+    }
+    const size_t b_cnv = align256(cnv.size() * 8);
+    const size_t b_tw64 = align256(tw64.size() * 8);
+    const size_t b_tw32 = align256(tw32.size() * 4);
+    char* d = nullptr;
+    hipError_t e = hipMalloc((void**)&d, b_cnv + b_tw64 + b_tw32);
+    if (e != hipSuccess) return fail(EWALD_ENOMEM, "plan tables: %s", hipGetErrorString(e));
+    pl->d_tables = d;
+    e = hipMemcpy(d, cnv.data(), cnv.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d + b_cnv, tw64.data(), tw64.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d + b_cnv + b_tw64, tw32.data(), tw32.size() * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "plan table upload");
+    for (int k = 0; k < 3; ++k) pl->d_cnv[k] = (double*)d + cnv_off[k];
+    pl->d_tw64 = d + b_cnv;
+    pl->d_tw32 = d + b_cnv + b_tw64;
+    return EWALD_OK;
+}
+
+int check_eval_args(ewald_plan_t plan, int64_t n, const void* x, const void* f, const void* o1,
+                    const void* o2, void* ws, int64_t wsb, Work* w)
+{
+    if (!plan) return fail(EWALD_EINVAL, "null plan");
+    const Plan* pl = reinterpret_cast<const Plan*>(plan);
+    if (n < 0) return fail(EWALD_EINVAL, "n = %lld < 0", (long long)n);
+    if (n > pl->p.n_max) return fail(EWALD_EINVAL, "n = %lld exceeds the plan's n_max = %lld", (long long)n, (long long)pl->p.n_max);
+    if (n == 0) return EWALD_OK;
+    if (!x || !f || !o1 || !o2) return fail(EWALD_EINVAL, "null array pointer");
+    if (!ws) return fail(EWALD_EINVAL, "null workspace");
+    if (((uintptr_t)ws & 255) != 0) return fail(EWALD_EINVAL, "workspace not 256-byte aligned");
+    const int64_t need = layout_work(*pl, n, (char*)ws, w);
+    if (wsb < need) return fail(EWALD_ENOMEM, "workspace of %lld bytes below the %lld needed", (long long)wsb, (long long)need);
+    return EWALD_OK;
+}
+
+enum class Out { Full, Parts, Spread, FarGrid };
+
+int run(ewald_plan_t plan, int64_t n64, const double* x, const double* f, void* o1, void* o2, void* ws,
+        int64_t wsb, void* stream, Out what)
+{
+    Work w;
+    int rc = check_eval_args(plan, n64, x, f, o1, what == Out::Parts ? o2 : o1, ws, wsb, &w);
+    if (rc != EWALD_OK || n64 == 0) return rc;
+    Plan* pl = reinterpret_cast<Plan*>(plan);
+    hipStream_t s = (hipStream_t)stream;
+    const int n = (int)n64;
+    const bool t = pl->timers && what != Out::Spread && what != Out::FarGrid;
+    hipError_t e;
+    auto mark = [&](int k) {
+        if (t) hipEventRecord(pl->ev[k], s);
+    };
+    mark(0);
+    if ((e = launch_sort(*pl, w, n, x, f, s)) != hipSuccess) return hip_fail(e, "sort");
+    mark(1);
+    if (what == Out::Full || what == Out::Parts) {
+        if ((e = launch_p2p(*pl, w, n, s)) != hipSuccess) return hip_fail(e, "P2P");
+    }
+    mark(2);
+    if ((e = launch_p2g(*pl, w, n, s)) != hipSuccess) return hip_fail(e, "P2G");
+    mark(3);
+    const size_t gbytes = (size_t)3 * pl->g.ncells * (pl->mode == EWALD_FP64 ? 8 : 4);
+    if (what == Out::Spread) {
+        e = hipMemcpyAsync(o1, w.grid, gbytes, hipMemcpyDeviceToDevice, s);
+        return e == hipSuccess ? EWALD_OK : hip_fail(e, "grid copy");
+    }
+    if ((e = launch_fgc(*pl, w, s, true, true)) != hipSuccess) return hip_fail(e, "FFT/CNV/IFFT");
+    mark(4);
+    if (what == Out::FarGrid) {
+        e = hipMemcpyAsync(o1, w.grid, gbytes, hipMemcpyDeviceToDevice, s);
+        return e == hipSuccess ? EWALD_OK : hip_fail(e, "grid copy");
+    }
+    if (what == Out::Full)
+        e = launch_g2p(*pl, w, n, f, (double*)o1, nullptr, nullptr, s);
+    else
+        e = launch_g2p(*pl, w, n, f, nullptr, (double*)o1, (double*)o2, s);
+    if (e != hipSuccess) return hip_fail(e, "G2P");
+    mark(5);
+    if (t) pl->ev_valid = true;
+    return EWALD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ewald_plan_create(const ewald_params* params, ewald_plan_t* plan_out)
+{
+    if (!params || !plan_out) return fail(EWALD_EINVAL, "null argument");
+    *plan_out = nullptr;
+    Plan* pl = new (std::nothrow) Plan();
+    if (!pl) return fail(EWALD_ENOMEM, "plan allocation");
+    std::memset(pl, 0, sizeof *pl);
+    int rc = validate_and_resolve(params, pl);
+    if (rc == EWALD_OK) {
+        hipError_t e = hipGetDevice(&pl->device);
+        if (e != hipSuccess) rc = hip_fail(e, "hipGetDevice");
+    }
+    if (rc == EWALD_OK) rc = build_tables(pl);
+    if (rc == EWALD_OK && pl->timers) {
+        for (int k = 0; k <= kNumStages && rc == EWALD_OK; ++k) {
+            hipError_t e = hipEventCreate(&pl->ev[k]);
+            if (e != hipSuccess) rc = hip_fail(e, "hipEventCreate");
+        }
+    }
+    if (rc != EWALD_OK) {
+        ewald_plan_destroy(reinterpret_cast<ewald_plan_t>(pl));
+        return rc;
+    }
+    *plan_out = reinterpret_cast<ewald_plan_t>(pl);
+    return EWALD_OK;
+}
+
+int ewald_resolve(const ewald_params* params, ewald_plan_info* info)
+{
+    if (!params || !info) return fail(EWALD_EINVAL, "null argument");
+    Plan* pl = new (std::nothrow) Plan();
+    if (!pl) return fail(EWALD_ENOMEM, "plan allocation");
+    std::memset(pl, 0, sizeof *pl);
+    const int rc = validate_and_resolve(params, pl);
+    if (rc == EWALD_OK) *info = pl->info;
+    delete pl;
+    return rc;
+}
+
+int ewald_plan_get_info(ewald_plan_t plan, ewald_plan_info* info)
+{
+    if (!plan || !info) return fail(EWALD_EINVAL, "null argument");
+    *info = reinterpret_cast<Plan*>(plan)->info;
+    return EWALD_OK;
+}
+
+int ewald_plan_destroy(ewald_plan_t plan)
+{
+    if (!plan) return EWALD_OK;
+    Plan* pl = reinterpret_cast<Plan*>(plan);
+    if (pl->d_tables) hipFree(pl->d_tables);
+    for (int k = 0; k <= kNumStages; ++k)
+        if (pl->ev[k]) hipEventDestroy(pl->ev[k]);
+    delete pl;
+    return EWALD_OK;
+}
+
+int64_t ewald_workspace_bytes(ewald_plan_t plan, int64_t n)
+{
+    if (!plan) return fail(EWALD_EINVAL, "null plan");
+    if (n < 0) return fail(EWALD_EINVAL, "n = %lld < 0", (long long)n);
+    return layout_work(*reinterpret_cast<Plan*>(plan), n, nullptr, nullptr);
+}
+
+int ewald_eval(ewald_plan_t plan, int64_t n, const double* x, const double* f, double* u, void* workspace,
+               int64_t workspace_bytes, void* stream)
+{
+    return run(plan, n, x, f, u, u, workspace, workspace_bytes, stream, Out::Full);
+}
+
+int ewald_eval_parts(ewald_plan_t plan, int64_t n, const double* x, const double* f, double* u_near,
+                     double* u_far, void* workspace, int64_t workspace_bytes, void* stream)
+{
+    return run(plan, n, x, f, u_near, u_far, workspace, workspace_bytes, stream, Out::Parts);
+}
+
+int ewald_spread(ewald_plan_t plan, int64_t n, const double* x, const double* f, void* grid, void* workspace,
+                 int64_t workspace_bytes, void* stream)
+{
+    return run(plan, n, x, f, grid, grid, workspace, workspace_bytes, stream, Out::Spread);
+}
+
+int ewald_far_grid(ewald_plan_t plan, int64_t n, const double* x, const double* f, void* grid,
+                   void* workspace, int64_t workspace_bytes, void* stream)
+{
+    return run(plan, n, x, f, grid, grid, workspace, workspace_bytes, stream, Out::FarGrid);
+}
+
+int ewald_stage_ms(ewald_plan_t plan, float* ms, int32_t count)
+{
+    if (!plan || !ms || count < 0) return fail(EWALD_EINVAL, "bad argument");
+    Plan* pl = reinterpret_cast<Plan*>(plan);
+    if (!pl->timers) return fail(EWALD_EINVAL, "plan was created without EWALD_FLAG_STAGE_TIMERS");
+    if (!pl->ev_valid) return fail(EWALD_EINVAL, "no timed evaluation recorded yet");
+    float v[kNumStages];
+    for (int k = 0; k < kNumStages - 1; ++k) {
+        hipError_t e = hipEventElapsedTime(&v[k], pl->ev[k], pl->ev[k + 1]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    }
+    hipError_t e = hipEventElapsedTime(&v[kNumStages - 1], pl->ev[0], pl->ev[kNumStages - 1]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    const int k = std::min<int>(count, kNumStages);
+    for (int i = 0; i < k; ++i) ms[i] = v[i];
+    return k;
+}
+
+const char* ewald_last_error(void) { return g_err.c_str(); }
+
+const char* ewald_version(void) { return "paper_2606_19059_amd 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,334 @@
+// Fourier grid convolution (FGC): FFT, CNV, IFFT of Sec. 2.2 steps (2)-(4), hand-written
+// for gfx950.
+//
+// The three real grid components phi_d (M1 x M2 x M3, z fastest) are transformed in
+// place into the half spectrum kz = 0..M3/2-1 (the kz = M3/2 Nyquist plane is zero after
+// CNV and is never stored, so the spectrum occupies exactly the real grid's bytes):
+//   pass 1  z, real-to-complex: each z-line is read as M3/2 complex numbers, transformed
+//           with a length-M3/2 complex FFT and unpacked into the half spectrum;
+//   pass 2  y, complex, strided;
+//   pass 3  x, complex, strided, for the three components together: forward FFT, then
+//           the diagonal CNV scaling of eq. (sca) with Ghat^F of eq. (GFk) evaluated in
+//           FP64, then the inverse FFT, without leaving LDS;
+//   pass 4  y inverse;
+//   pass 5  z, complex-to-real (the inverse of pass 1).
+// Each 1D transform is a Stockham radix-4 (plus one radix-2 stage for odd log2 n)
+// autosort FFT held in LDS, one workgroup per batch of adjacent columns (adjacent in
+// memory, so every row of a batch is one contiguous read).  Twiddles come from FP64 host
+// tables.  The k = 0 mode and the Nyquist planes are set to zero; the half-spectrum
+// convolution is enough because every field involved is real (Sec. 3.5).  The global
+// scale h1 h2 h3 / (M1 M2 M3) of the DFT round trip and of eq. (g2p) is folded into the
+// CNV tables, so the inverse transforms are unnormalised.
+#include "internal.h"
+
+namespace ewald {
+
+namespace {
+
+template <typename T>
+struct C2 {
+    T x, y;
+};
+
+template <typename T>
+__device__ inline C2<T> cmul(C2<T> a, C2<T> b)
+{
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+template <typename T>
+__device__ inline C2<T> cadd(C2<T> a, C2<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ inline C2<T> csub(C2<T> a, C2<T> b) { return {a.x - b.x, a.y - b.y}; }
+
+// Batched Stockham FFT of `ncols` columns of length n (power of two) stored as
+// a[e * ncols + c].  sign = -1 forward, +1 inverse (unnormalised).  `b` is scratch of
+// the same size.  Returns the buffer holding the result (a or b).  All threads of the
+// block take part; ends with a barrier.
+template <typename T>
+__device__ C2<T>* lds_fft(C2<T>* a, C2<T>* b, int n, int ncols, int sign, const C2<T>* __restrict__ tw)
+{
+    C2<T>* src = a;
+    C2<T>* dst = b;
+    const int cmask = ncols - 1;
+    int lc = 0;
+    while ((1 << lc) < ncols) ++lc;
+    for (int p = 1; p < n;) {
+        const int R = (n / p >= 4) ? 4 : 2;
+        const int Tn = n / R;
+        const int total = Tn * ncols;
+        const int tws = n / (p * R);
+        for (int bi = threadIdx.x; bi < total; bi += blockDim.x) {
+            const int c = bi & cmask;
+            const int i = bi >> lc;
+            const int k = i & (p - 1);
+            const int j = (i - k) * R + k;
+            if (R == 4) {
+                C2<T> u0 = src[(i)*ncols + c];
+                C2<T> u1 = src[(i + Tn) * ncols + c];
+                C2<T> u2 = src[(i + 2 * Tn) * ncols + c];
+                C2<T> u3 = src[(i + 3 * Tn) * ncols + c];
+                if (k) {
+                    C2<T> w1 = tw[(k * tws) & (n - 1)];
+                    C2<T> w2 = tw[(2 * k * tws) & (n - 1)];
+                    C2<T> w3 = tw[(3 * k * tws) & (n - 1)];
+                    if (sign > 0) {
+                        w1.y = -w1.y;
+                        w2.y = -w2.y;
+                        w3.y = -w3.y;
+                    }
+                    u1 = cmul(u1, w1);
+                    u2 = cmul(u2, w2);
+                    u3 = cmul(u3, w3);
+                }
+                const C2<T> t0 = cadd(u0, u2), t1 = csub(u0, u2), t2 = cadd(u1, u3), d = csub(u1, u3);
+                // forward: -i d ; inverse: +i d
+                const C2<T> rot = (sign < 0) ? C2<T>{d.y, -d.x} : C2<T>{-d.y, d.x};
+                dst[(j)*ncols + c] = cadd(t0, t2);
+                dst[(j + p) * ncols + c] = cadd(t1, rot);
+                dst[(j + 2 * p) * ncols + c] = csub(t0, t2);
+                dst[(j + 3 * p) * ncols + c] = csub(t1, rot);
+            } else {
+                C2<T> u0 = src[(i)*ncols + c];
+                C2<T> u1 = src[(i + Tn) * ncols + c];
+                if (k) {
+                    C2<T> w1 = tw[(k * tws) & (n - 1)];
+                    if (sign > 0) w1.y = -w1.y;
+                    u1 = cmul(u1, w1);
+                }
+                dst[(j)*ncols + c] = cadd(u0, u1);
+                dst[(j + p) * ncols + c] = csub(u0, u1);
+            }
+        }
+        __syncthreads();
+        C2<T>* tmp = src;
+        src = dst;
+        dst = tmp;
+        p *= R;
+    }
+    return src;
+}
+
+// ---- pass 1 / 5: z-lines, real <-> half spectrum ----
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_z(T* __restrict__ grid, int64_t ncells, int nlines, int H,
+                                               int ncols, int sign, const C2<T>* __restrict__ tw_half,
+                                               const C2<T>* __restrict__ tw_full)
+{
+    extern __shared__ unsigned char smem_raw[];
+    C2<T>* a = reinterpret_cast<C2<T>*>(smem_raw);
+    C2<T>* b = a + (size_t)H * ncols;
+    C2<T>* data = reinterpret_cast<C2<T>*>(grid + blockIdx.y * ncells);
+    const int line0 = blockIdx.x * ncols;
+    const int tot = H * ncols;
+
+    if (sign < 0) {
+        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+            const int c = idx / H, e = idx - c * H;
+            if (line0 + c < nlines) a[e * ncols + c] = data[(int64_t)(line0 + c) * H + e];
+            else a[e * ncols + c] = C2<T>{0, 0};
+        }
+        __syncthreads();
+        C2<T>* C = lds_fft<T>(a, b, H, ncols, -1, tw_half);
+        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+            const int c = idx / H, k = idx - c * H;
+            if (line0 + c >= nlines) continue;
+            const C2<T> ck = C[k * ncols + c];
+            const C2<T> cm0 = C[((H - k) & (H - 1)) * ncols + c];
+            const C2<T> cm = {cm0.x, -cm0.y};
+            const C2<T> E = {(T)0.5 * (ck.x + cm.x), (T)0.5 * (ck.y + cm.y)};
+            const C2<T> dd = csub(ck, cm);
+            const C2<T> O = {(T)0.5 * dd.y, (T)-0.5 * dd.x};  // -i/2 (ck - cm)
+            data[(int64_t)(line0 + c) * H + k] = cadd(E, cmul(tw_full[k], O));
+        }
+    } else {
+        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+            const int c = idx / H, e = idx - c * H;
+            if (line0 + c < nlines) b[e * ncols + c] = data[(int64_t)(line0 + c) * H + e];
+            else b[e * ncols + c] = C2<T>{0, 0};
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+            const int c = idx / H, k = idx - c * H;
+            C2<T> xk = b[k * ncols + c];
+            C2<T> xm;
+            if (k == 0) {
+                xk.y = 0;             // DC of a real line
+                xm = C2<T>{0, 0};     // Nyquist (zeroed by CNV)
+            } else {
+                const C2<T> v = b[(H - k) * ncols + c];
+                xm = C2<T>{v.x, -v.y};
+            }
+            const C2<T> E = cadd(xk, xm);
+            C2<T> w = tw_full[k];
+            w.y = -w.y;  // e^{+2 pi i k / M3}
+            const C2<T> O = cmul(csub(xk, xm), w);
+            a[k * ncols + c] = C2<T>{E.x - O.y, E.y + O.x};  // E + i O
+        }
+        __syncthreads();
+        C2<T>* z = lds_fft<T>(a, b, H, ncols, +1, tw_half);
+        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+            const int c = idx / H, e = idx - c * H;
+            if (line0 + c < nlines) data[(int64_t)(line0 + c) * H + e] = z[e * ncols + c];
+        }
+    }
+}
+
+// ---- pass 2 / 4: y-columns ----
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_y(T* __restrict__ grid, int64_t ncells, int M2, int H,
+                                               int ncols, int sign, const C2<T>* __restrict__ tw)
+{
+    extern __shared__ unsigned char smem_raw[];
+    C2<T>* a = reinterpret_cast<C2<T>*>(smem_raw);
+    C2<T>* b = a + (size_t)M2 * ncols;
+    C2<T>* data = reinterpret_cast<C2<T>*>(grid + blockIdx.y * ncells);
+    const int tiles_per_x = H / ncols;
+    const int x = blockIdx.x / tiles_per_x;
+    const int kz0 = (blockIdx.x - x * tiles_per_x) * ncols;
+    const int64_t base = (int64_t)x * M2 * H + kz0;
+    const int tot = M2 * ncols;
+    for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+        const int e = idx / ncols, c = idx - e * ncols;
+        a[idx] = data[base + (int64_t)e * H + c];
+    }
+    __syncthreads();
+    C2<T>* r = lds_fft<T>(a, b, M2, ncols, sign, tw);
+    for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+        const int e = idx / ncols, c = idx - e * ncols;
+        data[base + (int64_t)e * H + c] = r[idx];
+    }
+}
+
+// ---- pass 3: x-columns, forward FFT + CNV + inverse FFT, 3 components together ----
+
+struct CnvArgs {
+    double twopi_over_L[3];
+    double inv4xi2;
+    double eightpi;
+    const double* E0;  // per-axis factors (alpha/pi) exp(k^2 (1/(2 alpha) - 1/(4 xi^2))), scale folded in E0
+    const double* E1;
+    const double* E2;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_x_cnv(T* __restrict__ grid, int64_t ncells, int M1, int M2,
+                                                   int H, int ncols, int do_cnv, int do_inv,
+                                                   const C2<T>* __restrict__ tw, CnvArgs ca)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const int cols = 3 * ncols;
+    C2<T>* a = reinterpret_cast<C2<T>*>(smem_raw);
+    C2<T>* b = a + (size_t)M1 * cols;
+    const int tiles_per_y = H / ncols;
+    const int ky = blockIdx.x / tiles_per_y;
+    const int kz0 = (blockIdx.x - ky * tiles_per_y) * ncols;
+    const int64_t rowstride = (int64_t)M2 * H;  // complex elements between consecutive x
+    const int tot = M1 * cols;
+    for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+        const int e = idx / cols, cc = idx - e * cols;
+        const int comp = cc / ncols, c = cc - comp * ncols;
+        const C2<T>* data = reinterpret_cast<const C2<T>*>(grid + comp * ncells);
+        a[idx] = data[(int64_t)e * rowstride + (int64_t)ky * H + kz0 + c];
+    }
+    __syncthreads();
+    C2<T>* r = lds_fft<T>(a, b, M1, cols, -1, tw);
+    if (do_cnv) {
+        const int kys = (ky < M2 / 2) ? ky : ky - M2;
+        const double k1 = ca.twopi_over_L[1] * kys;
+        const double e1 = ca.E1[ky];
+        for (int idx = threadIdx.x; idx < M1 * ncols; idx += blockDim.x) {
+            const int kx = idx / ncols, c = idx - kx * ncols;
+            const int kz = kz0 + c;
+            const int kxs = (kx < M1 / 2) ? kx : kx - M1;
+            const double k0 = ca.twopi_over_L[0] * kxs;
+            const double k2 = ca.twopi_over_L[2] * kz;
+            const double K2 = k0 * k0 + k1 * k1 + k2 * k2;
+            double A = 0.0;
+            if (K2 > 0.0) A = ca.E0[kx] * e1 * ca.E2[kz] * ca.eightpi * (1.0 + K2 * ca.inv4xi2) / (K2 * K2);
+            C2<T>* p0 = &r[kx * cols + c];
+            C2<T>* p1 = &r[kx * cols + ncols + c];
+            C2<T>* p2 = &r[kx * cols + 2 * ncols + c];
+            const double q0r = p0->x, q0i = p0->y, q1r = p1->x, q1i = p1->y, q2r = p2->x, q2i = p2->y;
+            const double dr = k0 * q0r + k1 * q1r + k2 * q2r;
+            const double di = k0 * q0i + k1 * q1i + k2 * q2i;
+            *p0 = C2<T>{(T)(A * (K2 * q0r - k0 * dr)), (T)(A * (K2 * q0i - k0 * di))};
+            *p1 = C2<T>{(T)(A * (K2 * q1r - k1 * dr)), (T)(A * (K2 * q1i - k1 * di))};
+            *p2 = C2<T>{(T)(A * (K2 * q2r - k2 * dr)), (T)(A * (K2 * q2i - k2 * di))};
+        }
+        __syncthreads();
+    }
+    if (do_inv) r = lds_fft<T>(r, (r == a) ? b : a, M1, cols, +1, tw);
+    for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+        const int e = idx / cols, cc = idx - e * cols;
+        const int comp = cc / ncols, c = cc - comp * ncols;
+        C2<T>* data = reinterpret_cast<C2<T>*>(grid + comp * ncells);
+        data[(int64_t)e * rowstride + (int64_t)ky * H + kz0 + c] = r[idx];
+    }
+}
+
+inline int pow2_floor(int v)
+{
+    int p = 1;
+    while (p * 2 <= v) p *= 2;
+    return p;
+}
+
+template <typename T>
+hipError_t launch_fgc_t(const Plan& pl, const Work& w, hipStream_t s, bool inverse_too, bool cnv)
+{
+    const Geometry& g = pl.g;
+    const int M1 = g.M[0], M2 = g.M[1], M3 = g.M[2], H = M3 / 2;
+    const int64_t nc = g.ncells;
+    T* grid = (T*)w.grid;
+    const C2<T>* tw = (const C2<T>*)(sizeof(T) == 8 ? pl.d_tw64 : pl.d_tw32);
+    const C2<T>* tw0 = tw + pl.tw_off[0];
+    const C2<T>* tw1 = tw + pl.tw_off[1];
+    const C2<T>* twh = tw + pl.tw_off[2];
+    const C2<T>* twf = tw + pl.tw_off[3];
+    const int budget = (sizeof(T) == 8) ? 1024 : 2048;  // complex elements per buffer
+
+    // pass 1: z forward (R2C)
+    const int nlines = M1 * M2;
+    int ncz = pow2_floor(max(1, budget / H));
+    if (ncz > nlines) ncz = pow2_floor(nlines);
+    size_t shz = 2 * (size_t)H * ncz * sizeof(C2<T>);
+    dim3 gz((nlines + ncz - 1) / ncz, 3);
+    hipLaunchKernelGGL((k_fft_z<T>), gz, dim3(256), shz, s, grid, nc, nlines, H, ncz, -1, twh, twf);
+    // pass 2: y forward
+    int ncy = pow2_floor(max(1, budget / M2));
+    if (ncy > H) ncy = H;
+    size_t shy = 2 * (size_t)M2 * ncy * sizeof(C2<T>);
+    dim3 gy(M1 * (H / ncy), 3);
+    hipLaunchKernelGGL((k_fft_y<T>), gy, dim3(256), shy, s, grid, nc, M2, H, ncy, -1, tw1);
+    // pass 3: x forward + CNV (+ inverse)
+    int ncx = pow2_floor(max(1, budget / (3 * M1)));
+    if (ncx > H) ncx = H;
+    size_t shx = 2 * (size_t)3 * M1 * ncx * sizeof(C2<T>);
+    CnvArgs ca;
+    for (int d = 0; d < 3; ++d) ca.twopi_over_L[d] = 2.0 * M_PI / g.L[d];
+    ca.inv4xi2 = 1.0 / (4.0 * pl.xi * pl.xi);
+    ca.eightpi = 8.0 * M_PI;
+    ca.E0 = pl.d_cnv[0];
+    ca.E1 = pl.d_cnv[1];
+    ca.E2 = pl.d_cnv[2];
+    hipLaunchKernelGGL((k_fft_x_cnv<T>), dim3(M2 * (H / ncx)), dim3(256), shx, s, grid, nc, M1, M2, H, ncx,
+                       cnv ? 1 : 0, inverse_too ? 1 : 0, tw0, ca);
+    if (inverse_too) {
+        hipLaunchKernelGGL((k_fft_y<T>), gy, dim3(256), shy, s, grid, nc, M2, H, ncy, +1, tw1);
+        hipLaunchKernelGGL((k_fft_z<T>), gz, dim3(256), shz, s, grid, nc, nlines, H, ncz, +1, twh, twf);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fgc(const Plan& pl, const Work& w, hipStream_t s, bool inverse_too, bool cnv)
+{
+    if (pl.mode == EWALD_FP64) return launch_fgc_t<double>(pl, w, s, inverse_too, cnv);
+    return launch_fgc_t<float>(pl, w, s, inverse_too, cnv);
+}
+
+}  // namespace ewald

@@ -1,0 +1,114 @@
+// Internal declarations of the MI355X spectral Ewald library (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ewald.h"
+
+namespace ewald {
+
+constexpr int kNumStages = 6;  // bin/sort, P2P, P2G, FFT+CNV+IFFT, G2P+sum, total
+constexpr int kWave = 64;      // CDNA wavefront width
+
+// Grid / cell geometry, passed by value to kernels.
+struct Geometry {
+    double L[3];      // box sides
+    double h[3];      // grid spacing L/M
+    int M[3];         // grid points per dimension (powers of two)
+    int B;            // P2P tile edge in grid cells (power of two)
+    int log2B;
+    int NT[3];        // tiles per dimension (M / B)
+    int S[3];         // P2P stencil half-width in tiles
+    int ncells;       // M1 M2 M3 (sort bins = grid cells)
+    int ntiles;       // NT1 NT2 NT3
+};
+
+// Sort key of grid cell (cx, cy, cz): tile-major, then lexicographic inside the tile,
+// so that each P2P tile is one contiguous range of sorted particles.
+__host__ __device__ inline int cell_key(int cx, int cy, int cz, const Geometry& g)
+{
+    const int b = g.log2B, m = g.B - 1;
+    const int tile = ((cx >> b) * g.NT[1] + (cy >> b)) * g.NT[2] + (cz >> b);
+    return (tile << (3 * b)) | (((((cx & m) << b) | (cy & m)) << b) | (cz & m));
+}
+
+// Sorted particle record, FP64 mode: wrapped position (in [0, L)) and its grid cell, so
+// that every kernel uses the cell assignment of the sort (the fraction is x/h - c); 64 bytes.
+struct alignas(64) Rec64 {
+    double x[3];
+    int c[3];
+    int orig;  // original particle index
+    double f[3];
+};
+static_assert(sizeof(Rec64) == 64, "Rec64 layout");
+
+// FP32 bulk mode: fractions and forces in FP32, cell indices packed 10+10+10 bits; 32 bytes.
+struct alignas(32) Rec32 {
+    float t[3];
+    uint32_t cpack;
+    float f[3];
+    int orig;
+};
+static_assert(sizeof(Rec32) == 32, "Rec32 layout");
+
+__host__ __device__ inline uint32_t pack_cell(int cx, int cy, int cz)
+{
+    return (uint32_t)cx | ((uint32_t)cy << 10) | ((uint32_t)cz << 20);
+}
+
+struct Plan {
+    ewald_params p;        // resolved parameters
+    ewald_plan_info info;  // what get_info returns
+    Geometry g;
+    int P;                 // window support
+    double m;              // Gaussian shape
+    double beta;           // 2 m^2 / P^2: w0 = exp(-beta u^2), u = distance / h
+    double xi, rc;
+    int mode;              // EWALD_FP64 or EWALD_FP32_BULK
+    bool fp64acc;          // FP32 bulk: FP64 near-field accumulation
+    bool timers;
+    int device;
+    // device tables owned by the plan
+    void* d_tables;        // one allocation holding everything below
+    double* d_cnv[3];      // per-axis CNV factors E_d[k] (FP64), lengths M1, M2, M3/2
+    void* d_tw64;          // twiddles e^{-2 pi i j / n} (double2), per FFT length
+    void* d_tw32;          // same in float2
+    int tw_off[4];         // element offsets: axis0 (M1), axis1 (M2), half z (M3/2), full z (M3)
+    hipEvent_t ev[kNumStages + 1];
+    float stage_ms[kNumStages];
+    bool ev_valid;
+};
+
+// Device pointers carved out of the caller's workspace.
+struct Work {
+    int* key;        // [n]   sort key of each input particle
+    int* perm;       // [n]   sorted slot -> original index (also carried in records)
+    int* count;      // [ncells]   histogram, then scatter cursor
+    int* start;      // [ncells+1] exclusive scan of count
+    int* chunk_off;  // [ntiles+1] P2P wave work-list offsets
+    int* part;       // scan partials
+    void* rec;       // [n] Rec64 or Rec32, sorted order
+    double* u_near;  // [3][n] near field, sorted order
+    void* grid;      // 3 x ncells reals (double or float), then the in-place half spectrum
+    int64_t bytes;
+};
+
+int64_t layout_work(const Plan& pl, int64_t n, char* base, Work* w);
+
+// Launchers (all enqueue on `s`, return hipSuccess or the launch error).
+hipError_t launch_sort(const Plan& pl, const Work& w, int n, const double* x, const double* f,
+                       hipStream_t s);
+hipError_t launch_p2p(const Plan& pl, const Work& w, int n, hipStream_t s);
+hipError_t launch_p2g(const Plan& pl, const Work& w, int n, hipStream_t s);
+hipError_t launch_fgc(const Plan& pl, const Work& w, hipStream_t s, bool inverse_too, bool cnv);
+hipError_t launch_g2p(const Plan& pl, const Work& w, int n, const double* f, double* u,
+                      double* u_near_out, double* u_far_out, hipStream_t s);
+hipError_t launch_fill_i32(int* p, int64_t count, int value, hipStream_t s);
+
+// Exclusive scan of in[0..count) into out[0..count] (out[count] = total); `part`
+// needs scan_part_elems(count) ints.
+hipError_t launch_exclusive_scan(const int* in, int* out, int count, int* part, hipStream_t s);
+int scan_part_elems(int count);
+
+}  // namespace ewald

@@ -1,0 +1,207 @@
+// P2G: spreading of the 3-vector forces onto the uniform grid, eq. (p2g):
+//   phi(g_l) = sum_j sum_p w(g_l - y_j + p) f_j,  w separable, P points per axis.
+//
+// Atomic-free, owner-computes design for MI355X.  One wavefront owns an 8 x 8 patch of
+// grid lines along x (lane (ly, lz) owns line (y0+ly, z0+lz)) over an x-segment
+// [x0, x1), and sweeps the particle slabs of constant cell-x in increasing order.  Each
+// lane keeps P x-accumulators per component in registers: a particle in cell-x c adds
+// w_x[k] * w_y * w_z * f to the lane's points x = c - P/2 + 1 + k; after slab c has been
+// processed the point x = c - P/2 + 1 receives nothing more, so it is written once, to its
+// final value, and the register window shifts by one.  Every grid point is written by
+// exactly one lane, in a fixed particle order: deterministic, no atomics, no zero-fill.
+// The particles of a slab that can reach the patch (a (8+P-1)^2 window of cells) are
+// contiguous runs of the cell-sorted arrays; they are staged in LDS with their 3 x P
+// separable 1D weights (computed once per particle and wave), then every lane reads them
+// by broadcast.  The x direction is exact (no wasted work); in y and z a lane whose line is
+// outside the particle's P x P footprint multiplies by zero.
+#include "window.h"
+
+namespace ewald {
+
+namespace {
+
+constexpr int kPatch = 8;     // lines per patch edge (8 x 8 = 64 lanes)
+constexpr int kChunk = 32;    // particles staged per round
+constexpr int kMaxRuns = 320; // runs per slab (window rows x z-tile segments)
+
+template <typename T, int P>
+__global__ __launch_bounds__(64) void k_p2g_sweep(const typename RecView<T>::Rec* __restrict__ rec,
+                                                  const int* __restrict__ start, Geometry g,
+                                                  WinArgs<T> wa, int seg, int npy, int npz,
+                                                  T* __restrict__ grid)
+{
+    constexpr int W = kPatch + P - 1;
+    __shared__ int run_start[kMaxRuns];
+    __shared__ int run_pre[kMaxRuns + 1];
+    __shared__ T sw[kChunk][3][P];
+    __shared__ T sf[kChunk][3];
+    __shared__ int soff[kChunk];
+
+    const int lane = threadIdx.x;
+    const int item = blockIdx.x;
+    const int pz = item % npz, py = (item / npz) % npy, sx = item / (npz * npy);
+    const int M1 = g.M[0], M2 = g.M[1], M3 = g.M[2];
+    const int x0 = sx * seg, x1 = min(x0 + seg, M1);
+    const int y0 = py * kPatch, z0 = pz * kPatch;
+    const int ly = lane >> 3, lz = lane & 7;
+    const int B = g.B;
+
+    T acc[P][3];
+#pragma unroll
+    for (int k = 0; k < P; ++k) acc[k][0] = acc[k][1] = acc[k][2] = (T)0;
+
+    const int zlo = z0 - P / 2, zhi = z0 + kPatch - 1 + P / 2 - 1;
+    const int zt0 = floor_div(zlo, B), zt1 = floor_div(zhi, B);
+    const int nzs = zt1 - zt0 + 1;
+    const int R = W * nzs;
+    const int64_t nc = g.ncells;
+
+    for (int cxu = x0 - P / 2; cxu <= x1 + P / 2 - 2; ++cxu) {
+        const int cx = wrapi(cxu, M1);
+        // runs of this slab: one per (window row, z-tile segment)
+        int carry = 0;
+        for (int r0 = 0; r0 < R; r0 += kWave) {
+            const int r = r0 + lane;
+            int len = 0;
+            if (r < R) {
+                const int iy = r / nzs, zs = r - iy * nzs;
+                const int cy = wrapi(y0 - P / 2 + iy, M2);
+                const int zt = zt0 + zs;
+                const int au = max(zlo, zt * B), bu = min(zhi, zt * B + B - 1);
+                const int k0 = cell_key(cx, cy, wrapi(au, M3), g);
+                const int st = start[k0];
+                len = start[k0 + (bu - au) + 1] - st;
+                run_start[r] = st;
+            }
+            int inc = len;
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const int y = __shfl_up(inc, o, kWave);
+                if (lane >= o) inc += y;
+            }
+            if (r < R) run_pre[r + 1] = carry + inc;
+            carry += __shfl(inc, kWave - 1, kWave);
+        }
+        if (lane == 0) run_pre[0] = 0;
+        __syncthreads();
+        const int total = carry;
+
+        for (int base = 0; base < total; base += kChunk) {
+            const int cnt = min(kChunk, total - base);
+            if (lane < cnt) {
+                const int flat = base + lane;
+                int lo = 0, hi = R;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (run_pre[mid] <= flat) lo = mid; else hi = mid;
+                }
+                const int r = lo;
+                const int p = run_start[r] + (flat - run_pre[r]);
+                int c[3];
+                T t[3], f[3];
+                RecView<T>::load(rec[p], g, c, t, f);
+                const int iy = r / nzs, zs = r - iy * nzs;
+                const int oy = iy - (P - 1);  // stencil anchor - y0
+                const int czu = (zt0 + zs) * B + (c[2] & (B - 1));
+                const int oz = czu - P / 2 + 1 - z0;
+                soff[lane] = (oy + P) | ((oz + P) << 8);
+                T wv[P];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    window_weights<T, P>(t[d], wa, wv);
+#pragma unroll
+                    for (int k = 0; k < P; ++k) sw[lane][d][k] = wv[k];
+                    sf[lane][d] = f[d];
+                }
+            }
+            __syncthreads();
+            for (int q = 0; q < cnt; ++q) {
+                const int off = soff[q];
+                const int ky = ly - ((off & 255) - P);
+                const int kz = lz - ((off >> 8) - P);
+                const T wy = sw[q][1][min(max(ky, 0), P - 1)];
+                const T wz = sw[q][2][min(max(kz, 0), P - 1)];
+                const bool in = (unsigned)ky < (unsigned)P && (unsigned)kz < (unsigned)P;
+                const T wyz = in ? wy * wz : (T)0;
+                const T g0 = wyz * sf[q][0], g1 = wyz * sf[q][1], g2 = wyz * sf[q][2];
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    const T wx = sw[q][0][k];
+                    acc[k][0] += wx * g0;
+                    acc[k][1] += wx * g1;
+                    acc[k][2] += wx * g2;
+                }
+            }
+            __syncthreads();
+        }
+
+        const int xo = cxu - P / 2 + 1;
+        if (xo >= x0) {
+            const int64_t idx = ((int64_t)xo * M2 + (y0 + ly)) * M3 + (z0 + lz);
+            grid[idx] = acc[0][0];
+            grid[nc + idx] = acc[0][1];
+            grid[2 * nc + idx] = acc[0][2];
+        }
+#pragma unroll
+        for (int k = 0; k + 1 < P; ++k) {
+            acc[k][0] = acc[k + 1][0];
+            acc[k][1] = acc[k + 1][1];
+            acc[k][2] = acc[k + 1][2];
+        }
+        acc[P - 1][0] = acc[P - 1][1] = acc[P - 1][2] = (T)0;
+    }
+}
+
+template <typename T>
+WinArgs<T> win_args(const Plan& pl)
+{
+    WinArgs<T> wa;
+    wa.beta = (T)pl.beta;
+    for (int j = 0; j < kMaxP; ++j) wa.ratio[j] = (T)exp(-pl.beta * (2.0 * j + 1.0));
+    return wa;
+}
+
+template <typename T, int P>
+hipError_t launch_p2g_t(const Plan& pl, const Work& w, hipStream_t s)
+{
+    const Geometry& g = pl.g;
+    const int npy = g.M[1] / kPatch, npz = g.M[2] / kPatch;
+    // x-segment length: long enough that the (P-1)-slab warm-up is a small overhead,
+    // short enough to give the chip several waves per SIMD
+    int seg = g.M[0];
+    while (seg > 2 * P && (int64_t)(g.M[0] / seg) * npy * npz < 4096) seg >>= 1;
+    const int nseg = (g.M[0] + seg - 1) / seg;
+    const int blocks = nseg * npy * npz;
+    hipLaunchKernelGGL((k_p2g_sweep<T, P>), dim3(blocks), dim3(kWave), 0, s,
+                       (const typename RecView<T>::Rec*)w.rec, w.start, g, win_args<T>(pl), seg, npy,
+                       npz, (T*)w.grid);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_p2g_p(const Plan& pl, const Work& w, hipStream_t s)
+{
+    switch (pl.P) {
+    case 4: return launch_p2g_t<T, 4>(pl, w, s);
+    case 6: return launch_p2g_t<T, 6>(pl, w, s);
+    case 8: return launch_p2g_t<T, 8>(pl, w, s);
+    case 10: return launch_p2g_t<T, 10>(pl, w, s);
+    case 12: return launch_p2g_t<T, 12>(pl, w, s);
+    case 14: return launch_p2g_t<T, 14>(pl, w, s);
+    case 16: return launch_p2g_t<T, 16>(pl, w, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+int p2g_max_runs() { return kMaxRuns; }
+
+hipError_t launch_p2g(const Plan& pl, const Work& w, int n, hipStream_t s)
+{
+    (void)n;
+    if (pl.mode == EWALD_FP64) return launch_p2g_p<double>(pl, w, s);
+    return launch_p2g_p<float>(pl, w, s);
+}
+
+}  // namespace ewald

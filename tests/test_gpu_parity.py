@@ -1,0 +1,221 @@
+"""GPU parity of every stage against the CPU oracle (element by element).
+
+All calls go through the C ABI (``libewald.so``).  Tolerances (FP64 path):
+* P2G grid, far grid, P2P sum, far field: 1e-12 relative to the array's max -- the two
+  sides compute the same discrete sums in FP64 with different summation orders;
+* the full evaluation against the classical Ewald oracle: the requested tol (relative RMS).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import spectral as S
+from paper_2606_19059_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _E():
+    import paper_2606_19059_amd as E
+
+    E.load()
+    return E
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def maxrel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+# explicit parameter sets: (box, grid, xi, r_c, P, m)
+CASES = {
+    "cube32_P8": ((1.0, 1.0, 1.0), (32, 32, 32), 11.44, 0.387, 8, 4.8),
+    "aniso_P12": ((1.0, 1.3, 0.8), (16, 32, 64), 9.0, 0.30, 12, 5.8),
+    "grid8_P8": ((1.0, 1.0, 1.0), (8, 8, 8), 3.0, 0.45, 8, 4.6),
+    "long_P6": ((1.0, 1.0, 4.0), (16, 16, 64), 6.0, 0.5, 6, 4.1),
+    "cube16_P16": ((1.0, 1.0, 1.0), (16, 16, 16), 6.0, 0.45, 16, 6.6),
+}
+
+
+def make_plan(E, name, n_max):
+    box, grid, xi, rc, P, m = CASES[name]
+    return E.Plan(box, 1e-6, xi=xi, r_c=rc, grid=grid, P=P, window_shape=m, n_max=n_max)
+
+
+def test_tiny_eval_runs():
+    E = _E()
+    pl = make_plan(E, "cube32_P8", 100)
+    x, f = W.particles(100, (1, 1, 1), seed=1)
+    u = host(pl.eval(dev(x), dev(f)))
+    assert u.shape == (3, 100) and np.all(np.isfinite(u))
+
+
+@pytest.mark.parametrize("name,n", [("cube32_P8", 2000), ("aniso_P12", 1531), ("grid8_P8", 300),
+                                    ("long_P6", 2049), ("cube16_P16", 700)])
+def test_p2g_grid_matches_oracle(name, n):
+    E = _E()
+    box, grid, xi, rc, P, m = CASES[name]
+    pl = make_plan(E, name, n)
+    x, f = W.particles(n, box, seed=7)
+    g = host(pl.spread(dev(x), dev(f)))
+    ref = S.p2g(x, f, box, grid, P, m)
+    assert maxrel(g, ref) < 1e-12
+
+
+@pytest.mark.parametrize("name,n", [("cube32_P8", 2000), ("aniso_P12", 1531), ("long_P6", 900)])
+def test_far_grid_matches_oracle(name, n):
+    E = _E()
+    box, grid, xi, rc, P, m = CASES[name]
+    pl = make_plan(E, name, n)
+    x, f = W.particles(n, box, seed=8)
+    g = host(pl.far_grid(dev(x), dev(f)))
+    h3 = np.prod([box[d] / grid[d] for d in range(3)])
+    ref = h3 * S.far_grid(x, f, box, grid, xi, P, m)
+    assert maxrel(g, ref) < 1e-11
+
+
+@pytest.mark.parametrize("name,n", [("cube32_P8", 2000), ("aniso_P12", 1531), ("grid8_P8", 333),
+                                    ("long_P6", 1200), ("cube16_P16", 501)])
+def test_near_and_far_fields_match_oracle(name, n):
+    E = _E()
+    box, grid, xi, rc, P, m = CASES[name]
+    pl = make_plan(E, name, n)
+    x, f = W.particles(n, box, seed=9)
+    un, uf = pl.eval_parts(dev(x), dev(f))
+    un, uf = host(un), host(uf)
+    assert maxrel(un, oracle.real_space(x, f, box, xi, rc)) < 1e-12
+    assert maxrel(uf, S.far_field(x, f, box, grid, xi, P, m)) < 1e-11
+
+
+def test_full_eval_matches_spectral_oracle():
+    E = _E()
+    box, grid, xi, rc, P, m = CASES["aniso_P12"]
+    pl = make_plan(E, "aniso_P12", 1400)
+    x, f = W.particles(1400, box, seed=10)
+    u = host(pl.eval(dev(x), dev(f)))
+    ref = S.spectral_ewald(x, f, box, grid, xi, rc, P, m)
+    assert maxrel(u, ref) < 1e-12
+
+
+@pytest.mark.parametrize("tol,P", [(1e-6, 12), (1e-6, None), (1e-8, None), (1e-4, None)])
+def test_small_config_meets_tolerance(tol, P):
+    """N = 1000 uniform in the unit cube, 32^3 grid: relative RMS error <= tol."""
+    E = _E()
+    x, f = W.particles(1000, (1, 1, 1), seed=1)
+    pl = E.Plan((1, 1, 1), tol, grid=(32, 32, 32), P=P, n_max=1000)
+    u = host(pl.eval(dev(x), dev(f)))
+    ref = oracle.ewald_sum(x, f, (1, 1, 1))
+    err = oracle.rel_err(u, ref)
+    print("tol %g P %d err %.3e" % (tol, pl.info["P"], err))
+    assert err <= tol
+
+
+def test_configured_window_reports_its_error():
+    """The small case at its configured P = 8: the Gaussian window misses 1e-6 (reported)."""
+    E = _E()
+    x, f = W.particles(1000, (1, 1, 1), seed=1)
+    pl = E.Plan((1, 1, 1), 1e-6, grid=(32, 32, 32), P=8, n_max=1000)
+    u = host(pl.eval(dev(x), dev(f)))
+    err = oracle.rel_err(u, oracle.ewald_sum(x, f, (1, 1, 1)))
+    print("P=8 relative error %.3e (window model %.2e)" % (err, pl.info["err_window"]))
+    assert err < 5 * pl.info["err_window"]
+
+
+@pytest.mark.parametrize("box,n", [((1.0, 1.0, 2.0), 1500), ((1.0, 1.0, 4.0), 2000), ((0.7, 1.3, 1.1), 900)])
+def test_boxes_meet_tolerance(box, n):
+    E = _E()
+    x, f = W.particles(n, box, seed=3)
+    pl = E.Plan(box, 1e-6, n_max=n)
+    u = host(pl.eval(dev(x), dev(f)))
+    assert oracle.rel_err(u, oracle.ewald_sum(x, f, box)) <= 1e-6
+
+
+def test_clustered_blobs_meet_tolerance():
+    E = _E()
+    x, f = W.particles(3000, (1, 1, 1), seed=4, dist="blobs", n_blobs=5, sigma=0.01)
+    pl = E.Plan((1, 1, 1), 1e-6, grid=(32, 32, 32), n_max=3000)
+    u = host(pl.eval(dev(x), dev(f)))
+    assert oracle.rel_err(u, oracle.ewald_sum(x, f, (1, 1, 1))) <= 1e-6
+
+
+# ---------------------------------------------------------------- edge cases
+
+
+def test_zero_and_one_particle():
+    E = _E()
+    pl = make_plan(E, "cube32_P8", 10)
+    z = torch.empty((3, 0), dtype=torch.float64, device="cuda")
+    assert pl.eval(z, z).shape == (3, 0)
+    x = np.array([[0.31], [0.17], [0.74]])
+    f = np.array([[1.0], [-0.5], [0.25]])
+    u = host(pl.eval(dev(x), dev(f)))
+    ref = oracle.ewald_sum(x, f, (1, 1, 1))
+    assert oracle.rel_err(u, ref) < 1e-4  # P = 8 window
+
+
+def test_duplicates_and_wrapping():
+    """Exact duplicates skip each other (r = 0); positions outside the box wrap."""
+    E = _E()
+    box, grid, xi, rc, P, m = CASES["cube32_P8"]
+    pl = make_plan(E, "cube32_P8", 400)
+    x, f = W.particles(300, box, seed=11)
+    x = np.concatenate([x, x[:, :50]], axis=1)  # 50 exact duplicates
+    f = np.concatenate([f, 0.5 * f[:, :50]], axis=1)
+    shift = np.zeros_like(x)
+    shift[:, ::3] = np.array([[1.0], [-2.0], [3.0]])
+    un, uf = pl.eval_parts(dev(x + shift), dev(f))
+    assert maxrel(host(un), oracle.real_space(x, f, box, xi, rc)) < 1e-12
+    assert maxrel(host(uf), S.far_field(x, f, box, grid, xi, P, m)) < 1e-11
+
+
+def test_all_particles_in_one_cell():
+    E = _E()
+    box, grid, xi, rc, P, m = CASES["cube32_P8"]
+    pl = make_plan(E, "cube32_P8", 700)
+    rng = np.random.default_rng(2)
+    x = 0.5 + rng.random((3, 700)) * (1.0 / 32)
+    f = rng.standard_normal((3, 700))
+    un, uf = pl.eval_parts(dev(x), dev(f))
+    assert maxrel(host(un), oracle.real_space(x, f, box, xi, rc)) < 1e-12
+    assert maxrel(host(uf), S.far_field(x, f, box, grid, xi, P, m)) < 1e-11
+
+
+def test_deterministic_and_permutation_equivariant():
+    E = _E()
+    pl = make_plan(E, "aniso_P12", 3000)
+    x, f = W.particles(3000, CASES["aniso_P12"][0], seed=12)
+    a = host(pl.eval(dev(x), dev(f)))
+    b = host(pl.eval(dev(x), dev(f)))
+    assert np.array_equal(a, b)
+    p = np.random.default_rng(0).permutation(3000)
+    c = host(pl.eval(dev(x[:, p]), dev(f[:, p])))
+    assert np.max(np.abs(c - a[:, p])) < 1e-12 * np.max(np.abs(a))
+
+
+def test_errors_are_reported():
+    E = _E()
+    pl = make_plan(E, "cube32_P8", 100)
+    x, f = W.particles(100, (1, 1, 1), seed=1)
+    X, F = dev(x), dev(f)
+    small = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    with pytest.raises(E.EwaldError) as ei:
+        pl.eval(X, F, workspace=small)
+    assert ei.value.code == E.EWALD_ENOMEM
+    x2, f2 = W.particles(101, (1, 1, 1), seed=1)
+    with pytest.raises(E.EwaldError) as ei:
+        pl.eval(dev(x2), dev(f2))
+    assert ei.value.code == E.EWALD_EINVAL
+    # the plan still works afterwards
+    assert np.all(np.isfinite(host(pl.eval(X, F))))
