@@ -41,12 +41,13 @@ __device__ inline C2<T> cadd(C2<T> a, C2<T> b) { return {a.x + b.x, a.y + b.y}; 
 template <typename T>
 __device__ inline C2<T> csub(C2<T> a, C2<T> b) { return {a.x - b.x, a.y - b.y}; }
 
-// Batched Stockham FFT of `ncols` columns of length n (power of two) stored as
-// a[e * ncols + c].  sign = -1 forward, +1 inverse (unnormalised).  `b` is scratch of
-// the same size.  Returns the buffer holding the result (a or b).  All threads of the
-// block take part; ends with a barrier.
+// Batched Stockham FFT of ncomp x ncols columns of length n stored as
+// a[(comp * n + e) * ncols + c] (n and ncols powers of two).  sign = -1 forward, +1
+// inverse (unnormalised).  `b` is scratch of the same size.  Returns the buffer holding
+// the result (a or b).  All threads of the block take part; ends with a barrier.
 template <typename T>
-__device__ C2<T>* lds_fft(C2<T>* a, C2<T>* b, int n, int ncols, int sign, const C2<T>* __restrict__ tw)
+__device__ C2<T>* lds_fft(C2<T>* a, C2<T>* b, int n, int ncols, int ncomp, int sign,
+                          const C2<T>* __restrict__ tw)
 {
     C2<T>* src = a;
     C2<T>* dst = b;
@@ -56,18 +57,25 @@ __device__ C2<T>* lds_fft(C2<T>* a, C2<T>* b, int n, int ncols, int sign, const 
     for (int p = 1; p < n;) {
         const int R = (n / p >= 4) ? 4 : 2;
         const int Tn = n / R;
-        const int total = Tn * ncols;
+        const int per = Tn * ncols;  // butterflies per component (power of two)
+        int lp = 0;
+        while ((1 << lp) < per) ++lp;
+        const int total = per * ncomp;
         const int tws = n / (p * R);
         for (int bi = threadIdx.x; bi < total; bi += blockDim.x) {
-            const int c = bi & cmask;
-            const int i = bi >> lc;
+            const int comp = bi >> lp;
+            const int rem = bi & (per - 1);
+            const int c = rem & cmask;
+            const int i = rem >> lc;
             const int k = i & (p - 1);
             const int j = (i - k) * R + k;
+            C2<T>* sp = src + (size_t)comp * n * ncols;
+            C2<T>* dp = dst + (size_t)comp * n * ncols;
             if (R == 4) {
-                C2<T> u0 = src[(i)*ncols + c];
-                C2<T> u1 = src[(i + Tn) * ncols + c];
-                C2<T> u2 = src[(i + 2 * Tn) * ncols + c];
-                C2<T> u3 = src[(i + 3 * Tn) * ncols + c];
+                C2<T> u0 = sp[(i)*ncols + c];
+                C2<T> u1 = sp[(i + Tn) * ncols + c];
+                C2<T> u2 = sp[(i + 2 * Tn) * ncols + c];
+                C2<T> u3 = sp[(i + 3 * Tn) * ncols + c];
                 if (k) {
                     C2<T> w1 = tw[(k * tws) & (n - 1)];
                     C2<T> w2 = tw[(2 * k * tws) & (n - 1)];
@@ -84,20 +92,20 @@ __device__ C2<T>* lds_fft(C2<T>* a, C2<T>* b, int n, int ncols, int sign, const 
                 const C2<T> t0 = cadd(u0, u2), t1 = csub(u0, u2), t2 = cadd(u1, u3), d = csub(u1, u3);
                 // forward: -i d ; inverse: +i d
                 const C2<T> rot = (sign < 0) ? C2<T>{d.y, -d.x} : C2<T>{-d.y, d.x};
-                dst[(j)*ncols + c] = cadd(t0, t2);
-                dst[(j + p) * ncols + c] = cadd(t1, rot);
-                dst[(j + 2 * p) * ncols + c] = csub(t0, t2);
-                dst[(j + 3 * p) * ncols + c] = csub(t1, rot);
+                dp[(j)*ncols + c] = cadd(t0, t2);
+                dp[(j + p) * ncols + c] = cadd(t1, rot);
+                dp[(j + 2 * p) * ncols + c] = csub(t0, t2);
+                dp[(j + 3 * p) * ncols + c] = csub(t1, rot);
             } else {
-                C2<T> u0 = src[(i)*ncols + c];
-                C2<T> u1 = src[(i + Tn) * ncols + c];
+                C2<T> u0 = sp[(i)*ncols + c];
+                C2<T> u1 = sp[(i + Tn) * ncols + c];
                 if (k) {
                     C2<T> w1 = tw[(k * tws) & (n - 1)];
                     if (sign > 0) w1.y = -w1.y;
                     u1 = cmul(u1, w1);
                 }
-                dst[(j)*ncols + c] = cadd(u0, u1);
-                dst[(j + p) * ncols + c] = csub(u0, u1);
+                dp[(j)*ncols + c] = cadd(u0, u1);
+                dp[(j + p) * ncols + c] = csub(u0, u1);
             }
         }
         __syncthreads();
@@ -130,7 +138,7 @@ __global__ __launch_bounds__(256) void k_fft_z(T* __restrict__ grid, int64_t nce
             else a[e * ncols + c] = C2<T>{0, 0};
         }
         __syncthreads();
-        C2<T>* C = lds_fft<T>(a, b, H, ncols, -1, tw_half);
+        C2<T>* C = lds_fft<T>(a, b, H, ncols, 1, -1, tw_half);
         for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
             const int c = idx / H, k = idx - c * H;
             if (line0 + c >= nlines) continue;
@@ -167,7 +175,7 @@ __global__ __launch_bounds__(256) void k_fft_z(T* __restrict__ grid, int64_t nce
             a[k * ncols + c] = C2<T>{E.x - O.y, E.y + O.x};  // E + i O
         }
         __syncthreads();
-        C2<T>* z = lds_fft<T>(a, b, H, ncols, +1, tw_half);
+        C2<T>* z = lds_fft<T>(a, b, H, ncols, 1, +1, tw_half);
         for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
             const int c = idx / H, e = idx - c * H;
             if (line0 + c < nlines) data[(int64_t)(line0 + c) * H + e] = z[e * ncols + c];
@@ -195,7 +203,7 @@ __global__ __launch_bounds__(256) void k_fft_y(T* __restrict__ grid, int64_t nce
         a[idx] = data[base + (int64_t)e * H + c];
     }
     __syncthreads();
-    C2<T>* r = lds_fft<T>(a, b, M2, ncols, sign, tw);
+    C2<T>* r = lds_fft<T>(a, b, M2, ncols, 1, sign, tw);
     for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
         const int e = idx / ncols, c = idx - e * ncols;
         data[base + (int64_t)e * H + c] = r[idx];
@@ -219,27 +227,27 @@ __global__ __launch_bounds__(256) void k_fft_x_cnv(T* __restrict__ grid, int64_t
                                                    const C2<T>* __restrict__ tw, CnvArgs ca)
 {
     extern __shared__ unsigned char smem_raw[];
-    const int cols = 3 * ncols;
+    const int per = M1 * ncols;  // elements per component (power of two)
     C2<T>* a = reinterpret_cast<C2<T>*>(smem_raw);
-    C2<T>* b = a + (size_t)M1 * cols;
+    C2<T>* b = a + (size_t)3 * per;
     const int tiles_per_y = H / ncols;
     const int ky = blockIdx.x / tiles_per_y;
     const int kz0 = (blockIdx.x - ky * tiles_per_y) * ncols;
     const int64_t rowstride = (int64_t)M2 * H;  // complex elements between consecutive x
-    const int tot = M1 * cols;
+    const int tot = 3 * per;
     for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-        const int e = idx / cols, cc = idx - e * cols;
-        const int comp = cc / ncols, c = cc - comp * ncols;
+        const int comp = idx / per, rem = idx - comp * per;
+        const int e = rem / ncols, c = rem - e * ncols;
         const C2<T>* data = reinterpret_cast<const C2<T>*>(grid + comp * ncells);
         a[idx] = data[(int64_t)e * rowstride + (int64_t)ky * H + kz0 + c];
     }
     __syncthreads();
-    C2<T>* r = lds_fft<T>(a, b, M1, cols, -1, tw);
+    C2<T>* r = lds_fft<T>(a, b, M1, ncols, 3, -1, tw);
     if (do_cnv) {
         const int kys = (ky < M2 / 2) ? ky : ky - M2;
         const double k1 = ca.twopi_over_L[1] * kys;
         const double e1 = ca.E1[ky];
-        for (int idx = threadIdx.x; idx < M1 * ncols; idx += blockDim.x) {
+        for (int idx = threadIdx.x; idx < per; idx += blockDim.x) {
             const int kx = idx / ncols, c = idx - kx * ncols;
             const int kz = kz0 + c;
             const int kxs = (kx < M1 / 2) ? kx : kx - M1;
@@ -248,9 +256,9 @@ __global__ __launch_bounds__(256) void k_fft_x_cnv(T* __restrict__ grid, int64_t
             const double K2 = k0 * k0 + k1 * k1 + k2 * k2;
             double A = 0.0;
             if (K2 > 0.0) A = ca.E0[kx] * e1 * ca.E2[kz] * ca.eightpi * (1.0 + K2 * ca.inv4xi2) / (K2 * K2);
-            C2<T>* p0 = &r[kx * cols + c];
-            C2<T>* p1 = &r[kx * cols + ncols + c];
-            C2<T>* p2 = &r[kx * cols + 2 * ncols + c];
+            C2<T>* p0 = &r[idx];
+            C2<T>* p1 = &r[per + idx];
+            C2<T>* p2 = &r[2 * per + idx];
             const double q0r = p0->x, q0i = p0->y, q1r = p1->x, q1i = p1->y, q2r = p2->x, q2i = p2->y;
             const double dr = k0 * q0r + k1 * q1r + k2 * q2r;
             const double di = k0 * q0i + k1 * q1i + k2 * q2i;
@@ -260,10 +268,10 @@ __global__ __launch_bounds__(256) void k_fft_x_cnv(T* __restrict__ grid, int64_t
         }
         __syncthreads();
     }
-    if (do_inv) r = lds_fft<T>(r, (r == a) ? b : a, M1, cols, +1, tw);
+    if (do_inv) r = lds_fft<T>(r, (r == a) ? b : a, M1, ncols, 3, +1, tw);
     for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-        const int e = idx / cols, cc = idx - e * cols;
-        const int comp = cc / ncols, c = cc - comp * ncols;
+        const int comp = idx / per, rem = idx - comp * per;
+        const int e = rem / ncols, c = rem - e * ncols;
         C2<T>* data = reinterpret_cast<C2<T>*>(grid + comp * ncells);
         data[(int64_t)e * rowstride + (int64_t)ky * H + kz0 + c] = r[idx];
     }

@@ -155,14 +155,18 @@ def test_clustered_blobs_meet_tolerance():
 
 def test_zero_and_one_particle():
     E = _E()
+    box, grid, xi, rc, P, m = CASES["cube32_P8"]
     pl = make_plan(E, "cube32_P8", 10)
     z = torch.empty((3, 0), dtype=torch.float64, device="cuda")
     assert pl.eval(z, z).shape == (3, 0)
     x = np.array([[0.31], [0.17], [0.74]])
     f = np.array([[1.0], [-0.5], [0.25]])
     u = host(pl.eval(dev(x), dev(f)))
-    ref = oracle.ewald_sum(x, f, (1, 1, 1))
-    assert oracle.rel_err(u, ref) < 1e-4  # P = 8 window
+    assert maxrel(u, S.spectral_ewald(x, f, box, grid, xi, rc, P, m)) < 1e-12
+    # a tight plan reproduces the single-Stokeslet lattice value -(4/3) K f / L
+    hp = E.Plan(box, 1e-9, grid=(32, 32, 32), n_max=1)
+    u = host(hp.eval(dev(x), dev(f)))
+    assert oracle.rel_err(u, oracle.ewald_sum(x, f, box)) < 1e-8
 
 
 def test_duplicates_and_wrapping():
