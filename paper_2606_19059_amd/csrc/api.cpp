@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "screening.h"
 
 namespace ewald {
 int p2g_max_runs();
@@ -150,7 +151,7 @@ int64_t layout_work(const Plan& pl, int64_t n, char* base, Work* w)
     };
     const int64_t nn = std::max<int64_t>(n, 1);
     const size_t real = (pl.mode == EWALD_FP64) ? 8 : 4;
-    const size_t recsz = (pl.mode == EWALD_FP64) ? sizeof(Rec64) : sizeof(Rec32);
+    const size_t recsz = sizeof(Rec64);
     Work tmp;
     Work* o = w ? w : &tmp;
     o->key = (int*)take(4 * nn);
@@ -186,7 +187,8 @@ int validate_and_resolve(const ewald_params* in, Plan* pl)
         return fail(EWALD_EINVAL, "unknown precision mode %d", mode);
     if (p.precision & ~(0xff | EWALD_FLAG_P2P_FP64_ACC | EWALD_FLAG_STAGE_TIMERS))
         return fail(EWALD_EINVAL, "unknown precision flags 0x%x", p.precision);
-    if (mode == EWALD_FP32_BULK) return fail(EWALD_EUNSUPPORTED, "FP32 bulk mode is not built yet");
+    if (mode == EWALD_FP32_BULK && p.tol < 1e-7)
+        return fail(EWALD_EUNSUPPORTED, "tol = %g below 1e-7 needs the FP64 mode", p.tol);
     const bool grid_given = p.grid[0] > 0 && p.grid[1] > 0 && p.grid[2] > 0;
     if (grid_given)
         for (int d = 0; d < 3; ++d)
@@ -232,6 +234,9 @@ int validate_and_resolve(const ewald_params* in, Plan* pl)
     if (!(p.r_c > 0)) p.r_c = rc_from_xi(p.xi, third);
     if (!(p.xi > 0) || !std::isfinite(p.xi)) return fail(EWALD_EINVAL, "xi = %g invalid", p.xi);
     if (p.r_c > Lmin) return fail(EWALD_EINVAL, "r_c = %g exceeds the smallest box side %g", p.r_c, Lmin);
+    if (p.xi * p.r_c > kScreenXmax)
+        return fail(EWALD_EUNSUPPORTED, "xi r_c = %g above %g, the range of the near-field screening polynomial",
+                    p.xi * p.r_c, kScreenXmax);
     double hmin = 1e300;
     for (int d = 0; d < 3; ++d) hmin = std::min(hmin, p.box[d] / p.grid[d]);
     if (p.r_c < hmin) return fail(EWALD_EINVAL, "r_c = %g below the grid spacing %g", p.r_c, hmin);

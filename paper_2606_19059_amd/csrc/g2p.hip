@@ -4,75 +4,99 @@
 // then u_i = u^N_i + u^F_i - (4 xi/sqrt(pi)) f_i (Algorithm "se", SUM step, with the
 // self-term correction), scattered back to the caller's particle order.
 //
-// One lane per target in cell-sorted order, so a wave's 64 targets are spatially close
-// and their P^3 stencils overlap in the L1/L2 caches.  No atomics: each lane owns its
-// target.  The far field is accumulated in FP64 in both precision modes.
+// A wavefront gathers one target's P^3 stencil cooperatively (see k_g2p); consecutive
+// targets of a wave are cell-sorted neighbours, so their stencils overlap in L1.  No
+// atomics: each target's sum is owned by one wave.
 #include "window.h"
 
 namespace ewald {
 
 namespace {
 
-template <typename T, int P>
-__global__ __launch_bounds__(256) void k_g2p(int n, const typename RecView<T>::Rec* __restrict__ rec,
-                                             const T* __restrict__ grid, Geometry g, WinArgs<T> wa,
-                                             double self_coef, const double* __restrict__ u_near,
-                                             const double* __restrict__ f_in, double* __restrict__ u,
-                                             double* __restrict__ u_near_out,
-                                             double* __restrict__ u_far_out)
+template <typename T>
+__device__ inline T wave_sum(T v)
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const auto& r = rec[s];
-    int c[3];
-    T t[3], f[3];
-    RecView<T>::load(r, g, c, t, f);
-    const int orig = r.orig;
-    T wx[P], wy[P], wz[P];
-    window_weights<T, P>(t[0], wa, wx);
-    window_weights<T, P>(t[1], wa, wy);
-    window_weights<T, P>(t[2], wa, wz);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// One wavefront per group of kG2PPerWave consecutive (cell-sorted) targets, one target at
+// a time: lane l covers footprint points (y, z) = (l / P, l % P) (+ 64 per pass) and walks
+// the P points along x; z is fastest, so each load instruction reads runs of P consecutive
+// grid values (a few cache lines for the whole wave).  The 1D weights of the current
+// target are computed once (one lane per weight) and shared through LDS; the wave's
+// partial sums are reduced with shuffles, and lane 0 writes the result.
+constexpr int kG2PPerWave = 16;
+
+template <typename T, int P>
+__global__ __launch_bounds__(64) void k_g2p(int n, const typename RecView<T>::Rec* __restrict__ rec,
+                                            const T* __restrict__ grid, Geometry g, WinArgs<T> wa,
+                                            double self_coef, const double* __restrict__ u_near,
+                                            const double* __restrict__ f_in, double* __restrict__ u,
+                                            double* __restrict__ u_near_out,
+                                            double* __restrict__ u_far_out)
+{
+    constexpr int kPass = (P * P + kWave - 1) / kWave;
+    __shared__ T sw[3][P];
+    const int lane = threadIdx.x;
     const int M1 = g.M[0], M2 = g.M[1], M3 = g.M[2];
-    int iz[P];
-#pragma unroll
-    for (int k = 0; k < P; ++k) iz[k] = wrapi(c[2] - P / 2 + 1 + k, M3);
     const int64_t nc = g.ncells;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    for (int i = 0; i < P; ++i) {
-        const int gx = wrapi(c[0] - P / 2 + 1 + i, M1);
-        T b0 = 0, b1 = 0, b2 = 0;
-        for (int j = 0; j < P; ++j) {
-            const int gy = wrapi(c[1] - P / 2 + 1 + j, M2);
-            const int64_t row = ((int64_t)gx * M2 + gy) * M3;
-            T s0 = 0, s1 = 0, s2 = 0;
-#pragma unroll
-            for (int k = 0; k < P; ++k) {
-                const int64_t idx = row + iz[k];
-                s0 += wz[k] * grid[idx];
-                s1 += wz[k] * grid[nc + idx];
-                s2 += wz[k] * grid[2 * nc + idx];
-            }
-            b0 += wy[j] * s0;
-            b1 += wy[j] * s1;
-            b2 += wy[j] * s2;
-        }
-        a0 += (double)(wx[i] * b0);
-        a1 += (double)(wx[i] * b1);
-        a2 += (double)(wx[i] * b2);
-    }
     const int64_t nn = n;
-    const double n0 = u_near[s], n1 = u_near[nn + s], n2 = u_near[2 * nn + s];
-    if (u) {
-        u[orig] = n0 + a0 - self_coef * f_in[orig];
-        u[nn + orig] = n1 + a1 - self_coef * f_in[nn + orig];
-        u[2 * nn + orig] = n2 + a2 - self_coef * f_in[2 * nn + orig];
-    } else {
-        u_near_out[orig] = n0;
-        u_near_out[nn + orig] = n1;
-        u_near_out[2 * nn + orig] = n2;
-        u_far_out[orig] = a0;
-        u_far_out[nn + orig] = a1;
-        u_far_out[2 * nn + orig] = a2;
+    const int s0 = blockIdx.x * kG2PPerWave;
+    const int s1 = min(s0 + kG2PPerWave, n);
+    for (int s = s0; s < s1; ++s) {
+        const auto& r = rec[s];
+        int c[3];
+        T t[3], f[3];
+        RecView<T>::load(r, g, c, t, f);
+        if (lane < 3 * P) {
+            const int d = lane / P, j = lane - d * P;
+            const T td = (d == 0) ? t[0] : (d == 1 ? t[1] : t[2]);
+            const T uu = (T)(j - (P / 2 - 1)) - td;
+            T wv = exp(-wa.beta * uu * uu);
+            if (j == P - 1 && td == (T)0) wv = (T)0;  // open support
+            sw[d][j] = wv;
+        }
+        __syncthreads();
+        T a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll
+        for (int pass = 0; pass < kPass; ++pass) {
+            const int yz = pass * kWave + lane;
+            if (yz < P * P) {
+                const int jy = yz / P, kz = yz - jy * P;
+                const T wyz = sw[1][jy] * sw[2][kz];
+                const int gy = wrapi(c[1] - P / 2 + 1 + jy, M2);
+                const int gz = wrapi(c[2] - P / 2 + 1 + kz, M3);
+                const int64_t col = (int64_t)gy * M3 + gz;
+                for (int ix = 0; ix < P; ++ix) {
+                    const int gx = wrapi(c[0] - P / 2 + 1 + ix, M1);
+                    const int64_t idx = (int64_t)gx * M2 * M3 + col;
+                    const T wv = sw[0][ix] * wyz;
+                    a0 += wv * grid[idx];
+                    a1 += wv * grid[nc + idx];
+                    a2 += wv * grid[2 * nc + idx];
+                }
+            }
+        }
+        const double b0 = wave_sum((double)a0), b1 = wave_sum((double)a1), b2 = wave_sum((double)a2);
+        if (lane == 0) {
+            const int orig = r.orig;
+            const double n0 = u_near[s], n1 = u_near[nn + s], n2 = u_near[2 * nn + s];
+            if (u) {
+                u[orig] = n0 + b0 - self_coef * f_in[orig];
+                u[nn + orig] = n1 + b1 - self_coef * f_in[nn + orig];
+                u[2 * nn + orig] = n2 + b2 - self_coef * f_in[2 * nn + orig];
+            } else {
+                u_near_out[orig] = n0;
+                u_near_out[nn + orig] = n1;
+                u_near_out[2 * nn + orig] = n2;
+                u_far_out[orig] = b0;
+                u_far_out[nn + orig] = b1;
+                u_far_out[2 * nn + orig] = b2;
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -90,7 +114,7 @@ hipError_t launch_g2p_t(const Plan& pl, const Work& w, int n, const double* f, d
                         double* uf, hipStream_t s)
 {
     const double self_coef = 4.0 * pl.xi / sqrt(M_PI);
-    hipLaunchKernelGGL((k_g2p<T, P>), dim3((n + 255) / 256), dim3(256), 0, s, n,
+    hipLaunchKernelGGL((k_g2p<T, P>), dim3((n + kG2PPerWave - 1) / kG2PPerWave), dim3(kWave), 0, s, n,
                        (const typename RecView<T>::Rec*)w.rec, (const T*)w.grid, pl.g, win_args<T>(pl),
                        self_coef, w.u_near, f, u, un, uf);
     return hipGetLastError();

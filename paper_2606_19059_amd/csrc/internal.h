@@ -43,20 +43,6 @@ struct alignas(64) Rec64 {
 };
 static_assert(sizeof(Rec64) == 64, "Rec64 layout");
 
-// FP32 bulk mode: fractions and forces in FP32, cell indices packed 10+10+10 bits; 32 bytes.
-struct alignas(32) Rec32 {
-    float t[3];
-    uint32_t cpack;
-    float f[3];
-    int orig;
-};
-static_assert(sizeof(Rec32) == 32, "Rec32 layout");
-
-__host__ __device__ inline uint32_t pack_cell(int cx, int cy, int cz)
-{
-    return (uint32_t)cx | ((uint32_t)cy << 10) | ((uint32_t)cz << 20);
-}
-
 struct Plan {
     ewald_params p;        // resolved parameters
     ewald_plan_info info;  // what get_info returns
@@ -88,7 +74,7 @@ struct Work {
     int* start;      // [ncells+1] exclusive scan of count
     int* chunk_off;  // [ntiles+1] P2P wave work-list offsets
     int* part;       // scan partials
-    void* rec;       // [n] Rec64 or Rec32, sorted order
+    void* rec;       // [n] Rec64, sorted order
     double* u_near;  // [3][n] near field, sorted order
     void* grid;      // 3 x ncells reals (double or float), then the in-place half spectrum
     int64_t bytes;

@@ -21,14 +21,21 @@ namespace ewald {
 namespace {
 
 constexpr int kPatch = 8;     // lines per patch edge (8 x 8 = 64 lanes)
-constexpr int kChunk = 32;    // particles staged per round
+constexpr int kWaves = 4;     // waves per block, all owning the block's lines
+constexpr int kPerWave = 16;  // particles staged per wave and round
+constexpr int kChunk = kWaves * kPerWave;
 constexpr int kMaxRuns = 320; // runs per slab (window rows x z-tile segments)
 
-template <typename T, int P>
-__global__ __launch_bounds__(64) void k_p2g_sweep(const typename RecView<T>::Rec* __restrict__ rec,
-                                                  const int* __restrict__ start, Geometry g,
-                                                  WinArgs<T> wa, int seg, int npy, int npz,
-                                                  T* __restrict__ grid)
+// T: arithmetic and accumulation precision; TG: grid element type (the FP32 bulk mode
+// accumulates in FP64 -- the same VALU rate as FP32 without packed math -- and stores FP32).
+// A block of kWaves waves owns one (patch, x-segment): every wave keeps accumulators for
+// all 64 lines, takes every kWaves-th group of kPerWave particles of each slab, and at each
+// output step the waves' partial sums are added in a fixed order through LDS.
+template <typename T, typename TG, int P>
+__global__ __launch_bounds__(kWaves * 64) void k_p2g_sweep(const typename RecView<T>::Rec* __restrict__ rec,
+                                                           const int* __restrict__ start, Geometry g,
+                                                           WinArgs<T> wa, int seg, int npy, int npz,
+                                                           TG* __restrict__ grid)
 {
     constexpr int W = kPatch + P - 1;
     __shared__ int run_start[kMaxRuns];
@@ -36,8 +43,10 @@ __global__ __launch_bounds__(64) void k_p2g_sweep(const typename RecView<T>::Rec
     __shared__ T sw[kChunk][3][P];
     __shared__ T sf[kChunk][3];
     __shared__ int soff[kChunk];
+    __shared__ T red[kWaves - 1][3][64];
 
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
+    const int wid = tid >> 6, lane = tid & 63;
     const int item = blockIdx.x;
     const int pz = item % npz, py = (item / npz) % npy, sx = item / (npz * npy);
     const int M1 = g.M[0], M2 = g.M[1], M3 = g.M[2];
@@ -58,38 +67,42 @@ __global__ __launch_bounds__(64) void k_p2g_sweep(const typename RecView<T>::Rec
 
     for (int cxu = x0 - P / 2; cxu <= x1 + P / 2 - 2; ++cxu) {
         const int cx = wrapi(cxu, M1);
-        // runs of this slab: one per (window row, z-tile segment)
+        // runs of this slab: one per (window row, z-tile segment); wave 0 builds the table
         int carry = 0;
-        for (int r0 = 0; r0 < R; r0 += kWave) {
-            const int r = r0 + lane;
-            int len = 0;
-            if (r < R) {
-                const int iy = r / nzs, zs = r - iy * nzs;
-                const int cy = wrapi(y0 - P / 2 + iy, M2);
-                const int zt = zt0 + zs;
-                const int au = max(zlo, zt * B), bu = min(zhi, zt * B + B - 1);
-                const int k0 = cell_key(cx, cy, wrapi(au, M3), g);
-                const int st = start[k0];
-                len = start[k0 + (bu - au) + 1] - st;
-                run_start[r] = st;
-            }
-            int inc = len;
+        if (wid == 0) {
+            for (int r0 = 0; r0 < R; r0 += kWave) {
+                const int r = r0 + lane;
+                int len = 0;
+                if (r < R) {
+                    const int iy = r / nzs, zs = r - iy * nzs;
+                    const int cy = wrapi(y0 - P / 2 + iy, M2);
+                    const int zt = zt0 + zs;
+                    const int au = max(zlo, zt * B), bu = min(zhi, zt * B + B - 1);
+                    const int k0 = cell_key(cx, cy, wrapi(au, M3), g);
+                    const int st = start[k0];
+                    len = start[k0 + (bu - au) + 1] - st;
+                    run_start[r] = st;
+                }
+                int inc = len;
 #pragma unroll
-            for (int o = 1; o < kWave; o <<= 1) {
-                const int y = __shfl_up(inc, o, kWave);
-                if (lane >= o) inc += y;
+                for (int o = 1; o < kWave; o <<= 1) {
+                    const int y = __shfl_up(inc, o, kWave);
+                    if (lane >= o) inc += y;
+                }
+                if (r < R) run_pre[r + 1] = carry + inc;
+                carry += __shfl(inc, kWave - 1, kWave);
             }
-            if (r < R) run_pre[r + 1] = carry + inc;
-            carry += __shfl(inc, kWave - 1, kWave);
+            if (lane == 0) run_pre[0] = 0;
         }
-        if (lane == 0) run_pre[0] = 0;
         __syncthreads();
-        const int total = carry;
+        const int total = run_pre[R];
 
         for (int base = 0; base < total; base += kChunk) {
-            const int cnt = min(kChunk, total - base);
+            // each wave stages its own kPerWave particles of the chunk
+            const int q0 = wid * kPerWave;
+            const int cnt = max(0, min(kPerWave, total - base - q0));
             if (lane < cnt) {
-                const int flat = base + lane;
+                const int flat = base + q0 + lane;
                 int lo = 0, hi = R;
                 while (hi - lo > 1) {
                     const int mid = (lo + hi) >> 1;
@@ -104,18 +117,19 @@ __global__ __launch_bounds__(64) void k_p2g_sweep(const typename RecView<T>::Rec
                 const int oy = iy - (P - 1);  // stencil anchor - y0
                 const int czu = (zt0 + zs) * B + (c[2] & (B - 1));
                 const int oz = czu - P / 2 + 1 - z0;
-                soff[lane] = (oy + P) | ((oz + P) << 8);
+                const int q = q0 + lane;
+                soff[q] = (oy + P) | ((oz + P) << 8);
                 T wv[P];
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
                     window_weights<T, P>(t[d], wa, wv);
 #pragma unroll
-                    for (int k = 0; k < P; ++k) sw[lane][d][k] = wv[k];
-                    sf[lane][d] = f[d];
+                    for (int k = 0; k < P; ++k) sw[q][d][k] = wv[k];
+                    sf[q][d] = f[d];
                 }
             }
             __syncthreads();
-            for (int q = 0; q < cnt; ++q) {
+            for (int q = q0; q < q0 + cnt; ++q) {
                 const int off = soff[q];
                 const int ky = ly - ((off & 255) - P);
                 const int kz = lz - ((off >> 8) - P);
@@ -137,10 +151,25 @@ __global__ __launch_bounds__(64) void k_p2g_sweep(const typename RecView<T>::Rec
 
         const int xo = cxu - P / 2 + 1;
         if (xo >= x0) {
-            const int64_t idx = ((int64_t)xo * M2 + (y0 + ly)) * M3 + (z0 + lz);
-            grid[idx] = acc[0][0];
-            grid[nc + idx] = acc[0][1];
-            grid[2 * nc + idx] = acc[0][2];
+            if (wid > 0) {
+                red[wid - 1][0][lane] = acc[0][0];
+                red[wid - 1][1][lane] = acc[0][1];
+                red[wid - 1][2][lane] = acc[0][2];
+            }
+            __syncthreads();
+            if (wid == 0) {
+                T v0 = acc[0][0], v1 = acc[0][1], v2 = acc[0][2];
+#pragma unroll
+                for (int k = 0; k < kWaves - 1; ++k) {
+                    v0 += red[k][0][lane];
+                    v1 += red[k][1][lane];
+                    v2 += red[k][2][lane];
+                }
+                const int64_t idx = ((int64_t)xo * M2 + (y0 + ly)) * M3 + (z0 + lz);
+                grid[idx] = (TG)v0;
+                grid[nc + idx] = (TG)v1;
+                grid[2 * nc + idx] = (TG)v2;
+            }
         }
 #pragma unroll
         for (int k = 0; k + 1 < P; ++k) {
@@ -149,6 +178,7 @@ __global__ __launch_bounds__(64) void k_p2g_sweep(const typename RecView<T>::Rec
             acc[k][2] = acc[k + 1][2];
         }
         acc[P - 1][0] = acc[P - 1][1] = acc[P - 1][2] = (T)0;
+        __syncthreads();
     }
 }
 
@@ -161,7 +191,7 @@ WinArgs<T> win_args(const Plan& pl)
     return wa;
 }
 
-template <typename T, int P>
+template <typename TG, int P>
 hipError_t launch_p2g_t(const Plan& pl, const Work& w, hipStream_t s)
 {
     const Geometry& g = pl.g;
@@ -169,12 +199,11 @@ hipError_t launch_p2g_t(const Plan& pl, const Work& w, hipStream_t s)
     // x-segment length: long enough that the (P-1)-slab warm-up is a small overhead,
     // short enough to give the chip several waves per SIMD
     int seg = g.M[0];
-    while (seg > 2 * P && (int64_t)(g.M[0] / seg) * npy * npz < 4096) seg >>= 1;
+    while (seg > 4 * P && (int64_t)(g.M[0] / seg) * npy * npz < 1024) seg >>= 1;
     const int nseg = (g.M[0] + seg - 1) / seg;
     const int blocks = nseg * npy * npz;
-    hipLaunchKernelGGL((k_p2g_sweep<T, P>), dim3(blocks), dim3(kWave), 0, s,
-                       (const typename RecView<T>::Rec*)w.rec, w.start, g, win_args<T>(pl), seg, npy,
-                       npz, (T*)w.grid);
+    hipLaunchKernelGGL((k_p2g_sweep<double, TG, P>), dim3(blocks), dim3(kWaves * kWave), 0, s, (const Rec64*)w.rec,
+                       w.start, g, win_args<double>(pl), seg, npy, npz, (TG*)w.grid);
     return hipGetLastError();
 }
 

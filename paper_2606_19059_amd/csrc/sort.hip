@@ -101,26 +101,6 @@ __global__ void k_gather64(int n, const double* __restrict__ x, const double* __
     rec[s] = r;
 }
 
-__global__ void k_gather32(int n, const double* __restrict__ x, const double* __restrict__ f,
-                           const int* __restrict__ perm, Geometry g, Rec32* __restrict__ rec)
-{
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const int i = perm[s];
-    Rec32 r;
-    int c[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        double t, wx;
-        cell_of(x[(int64_t)d * n + i], g.L[d], g.h[d], g.M[d], c[d], t, wx);
-        r.t[d] = (float)t;
-        r.f[d] = (float)f[(int64_t)d * n + i];
-    }
-    r.cpack = pack_cell(c[0], c[1], c[2]);
-    r.orig = i;
-    rec[s] = r;
-}
-
 // Number of 64-target waves per P2P tile.
 __global__ void k_tile_chunks(Geometry g, const int* __restrict__ start, int* __restrict__ chunks)
 {
@@ -254,12 +234,8 @@ hipError_t launch_sort(const Plan& pl, const Work& w, int n, const double* x, co
     hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, w.key, w.count, w.perm);
     hipLaunchKernelGGL(k_cell_order, dim3(blocks_for(g.ncells, 256)), dim3(256), 0, s, g.ncells, w.start,
                        w.perm, 512);
-    if (pl.mode == EWALD_FP64)
-        hipLaunchKernelGGL(k_gather64, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, x, f, w.perm, g,
-                           (Rec64*)w.rec);
-    else
-        hipLaunchKernelGGL(k_gather32, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, x, f, w.perm, g,
-                           (Rec32*)w.rec);
+    hipLaunchKernelGGL(k_gather64, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, x, f, w.perm, g,
+                       (Rec64*)w.rec);
     // P2P work list: waves per tile, then their offsets
     hipLaunchKernelGGL(k_tile_chunks, dim3(blocks_for(g.ntiles, 256)), dim3(256), 0, s, g, w.start,
                        w.count);

@@ -55,16 +55,14 @@ struct RecView<double> {
 
 template <>
 struct RecView<float> {
-    using Rec = Rec32;
-    __device__ static inline void load(const Rec32& r, const Geometry&, int c[3], float t[3], float f[3])
+    using Rec = Rec64;
+    __device__ static inline void load(const Rec64& r, const Geometry& g, int c[3], float t[3], float f[3])
     {
-        c[0] = (int)(r.cpack & 1023u);
-        c[1] = (int)((r.cpack >> 10) & 1023u);
-        c[2] = (int)((r.cpack >> 20) & 1023u);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            t[d] = r.t[d];
-            f[d] = r.f[d];
+            c[d] = r.c[d];
+            t[d] = (float)(r.x[d] / g.h[d] - (double)r.c[d]);
+            f[d] = (float)r.f[d];
         }
     }
 };

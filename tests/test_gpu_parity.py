@@ -223,3 +223,55 @@ def test_errors_are_reported():
     assert ei.value.code == E.EWALD_EINVAL
     # the plan still works afterwards
     assert np.all(np.isfinite(host(pl.eval(X, F))))
+
+
+# ---------------------------------------------------------------- FP32 bulk mode
+# P2P formula, FFT and G2P in FP32 (P2G accumulates in FP64, stores FP32); positions,
+# the cutoff test, the Fourier-space scaling, self term and sum in FP64.
+
+
+def make_plan32(E, name, n_max, **kw):
+    box, grid, xi, rc, P, m = CASES[name]
+    return E.Plan(box, 1e-5, xi=xi, r_c=rc, grid=grid, P=P, window_shape=m, n_max=n_max, precision="fp32", **kw)
+
+
+@pytest.mark.parametrize("name,n", [("cube32_P8", 2000), ("aniso_P12", 1531)])
+def test_fp32_stages_match_oracle(name, n):
+    E = _E()
+    box, grid, xi, rc, P, m = CASES[name]
+    pl = make_plan32(E, name, n)
+    x, f = W.particles(n, box, seed=21)
+    X, F = dev(x), dev(f)
+    g = pl.spread(X, F)
+    assert g.dtype == torch.float32
+    assert maxrel(host(g).astype(np.float64), S.p2g(x, f, box, grid, P, m)) < 1e-6
+    un, uf = pl.eval_parts(X, F)
+    assert maxrel(host(un), oracle.real_space(x, f, box, xi, rc)) < 2e-6
+    assert maxrel(host(uf), S.far_field(x, f, box, grid, xi, P, m)) < 2e-5
+
+
+@pytest.mark.parametrize("tol,acc", [(1e-4, False), (1e-5, False), (1e-6, False), (1e-7, True)])
+def test_fp32_meets_tolerance(tol, acc):
+    E = _E()
+    x, f = W.particles(1500, (1, 1, 1), seed=5)
+    pl = E.Plan((1, 1, 1), tol, grid=(32, 32, 32), n_max=1500, precision="fp32", p2p_fp64_acc=acc)
+    u = host(pl.eval(dev(x), dev(f)))
+    err = oracle.rel_err(u, oracle.ewald_sum(x, f, (1, 1, 1)))
+    print("fp32 tol %g P %d err %.3e" % (tol, pl.info["P"], err))
+    assert err <= tol
+
+
+def test_fp32_blobs_elongated_box():
+    E = _E()
+    box = (1.0, 1.0, 2.0)
+    x, f = W.particles(3000, box, seed=6, dist="blobs", n_blobs=6, sigma=0.01)
+    pl = E.Plan(box, 1e-5, n_max=3000, precision="fp32")
+    u = host(pl.eval(dev(x), dev(f)))
+    assert oracle.rel_err(u, oracle.ewald_sum(x, f, box)) <= 1e-5
+
+
+def test_fp32_rejects_tolerance_below_its_precision():
+    E = _E()
+    with pytest.raises(E.EwaldError) as ei:
+        E.Plan((1, 1, 1), 1e-9, grid=(32, 32, 32), n_max=10, precision="fp32")
+    assert ei.value.code == E.EWALD_EUNSUPPORTED
