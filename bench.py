@@ -41,6 +41,70 @@ def p2p_pairs_uniform(n, box, r_c):
     return n * (n - 1) / V * (4.0 / 3.0) * math.pi * r_c**3
 
 
+def stage_roofline(stages, n, ncell, P, real, pairs, alu_peak_tflops):
+    """Per-stage algorithmic work (see the design notes), achieved rate and fraction of the binding roof.
+
+    sort: bytes N (24 + 48 + 64 + 16) + 12 per cell; P2P: 60 flop per pair in r_c; P2G and G2P: 7 flop per
+    (particle, stencil point), bytes 64 per record + one pass over the 3-component grid (+ 72 per particle
+    written/gathered by G2P); FFT+CNV+IFFT: five passes, each reading and writing the 3-component grid.
+    """
+    out = {}
+
+    def put(name, ms, flops=None, nbytes=None, bound="hbm"):
+        if ms <= 0:
+            return
+        e = {"ms": ms}
+        if flops is not None:
+            e["TFLOPs"] = flops / (ms * 1e-3) / 1e12
+        if nbytes is not None:
+            e["GBs"] = nbytes / (ms * 1e-3) / 1e9
+        e["bound"] = bound
+        e["frac"] = (e["TFLOPs"] / alu_peak_tflops) if bound == "alu" else (e["GBs"] / HBM_PEAK_GBS)
+        out[name] = e
+
+    grid_bytes = 3 * ncell * real
+    put("sort", stages["sort"], nbytes=n * (24 + 48 + 64 + 16) + 12 * ncell)
+    if pairs:
+        put("p2p", stages["p2p"], flops=pairs * P2P_FLOPS_PER_PAIR, bound="alu")
+    put("p2g", stages["p2g"], flops=7.0 * n * P**3, nbytes=64 * n + grid_bytes, bound="alu")
+    put("fgc", stages["fgc"], nbytes=5 * 2 * grid_bytes)
+    put("g2p", stages["g2p"], flops=7.0 * n * P**3, nbytes=grid_bytes + (64 + 72) * n, bound="alu")
+    return out
+
+
+def serving_leg(n_requests):
+    """Stream of independent suspensions (N log-uniform in [1e3, 1e6], cubic or 1x1x2 box,
+    uniform or blobs, tol in {1e-4, 1e-6, 1e-8}): saturated throughput with every request
+    waiting at t = 0, then Poisson arrivals at 0.8 of that rate for p50/p99 latency."""
+    import torch
+
+    from paper_2606_19059_amd import serve
+    from paper_2606_19059_amd import workloads as W
+
+    reqs = W.serving_stream(n_requests, rate_per_s=0.0, seed=5)
+    jobs = serve.make_jobs(reqs)
+    srv = serve.Server(n_slots=4)
+    srv.run(jobs[: min(4, len(jobs))])  # plans, tables and workspaces become resident
+    torch.cuda.synchronize()
+    for j in jobs:
+        j.arrival = 0.0
+    sat = serve.summarize(srv.run(jobs))
+    rate = 0.8 * sat["requests"] / sat["wall_s"]
+    reqs = W.serving_stream(n_requests, rate_per_s=rate, seed=5)
+    jobs2 = serve.make_jobs(reqs)
+    load = serve.summarize(srv.run(jobs2))
+    return {
+        "workload": "c5: %d requests, N log-uniform [1e3, 1e6], boxes 1^3 or 1x1x2, uniform or blobs, "
+                    "tol in {1e-4, 1e-6, 1e-8} (FP32 bulk for tol >= 1e-6, FP64 below), 4 streams, "
+                    "admission by HBM footprint" % n_requests,
+        "saturated_particles_per_s": sat["particles_per_s"],
+        "offered_load": 0.8,
+        "p50_ms": load["p50_ms"],
+        "p99_ms": load["p99_ms"],
+        "particles_per_s": load["particles_per_s"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -51,6 +115,10 @@ def main():
     ap.add_argument("--precision", default=None)
     ap.add_argument("--cpu-sample", type=int, default=24, help="oracle targets for accuracy + CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=40,
+                    help="requests in the serving leg (Poisson stream of independent suspensions; 0: skip)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one device copy of this many MiB first (reference for HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -63,10 +131,18 @@ def main():
     import paper_2606_19059_amd as E
     from paper_2606_19059_amd import workloads as W
 
+    if args.copy_calibration_mib > 0:
+        nb = args.copy_calibration_mib << 20
+        src = torch.empty(nb, dtype=torch.uint8, device="cuda:0").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: %d bytes read, %d bytes written by one copy kernel" % (nb, nb))
+        del src, dst
+
     wl = W.WORKLOADS[args.config]
     precision = args.precision or wl.precision
-    if precision == "fp32":
-        precision = "fp64"  # FP32 bulk mode is not built yet: measure the FP64 path
     x_np, f_np = wl.make()
     dev = torch.device("cuda:0")
     x = torch.from_numpy(x_np).to(dev)
@@ -130,7 +206,8 @@ def main():
     peak = FP64_VECTOR_TFLOPS if precision == "fp64" else FP32_VECTOR_TFLOPS
     achieved = (pairs * P2P_FLOPS_PER_PAIR / p2p_s / 1e12) if pairs else None
     roofline = {
-        "kernel": "k_p2p64" if precision == "fp64" else "k_p2p32",
+        "kernel": "k_p2p<double, double>" if precision == "fp64" else "k_p2p<float, %s>" % (
+            "double" if (info["mode_flags"] & E.EWALD_FLAG_P2P_FP64_ACC or wl.tol < 1e-7) else "float"),
         "bound": "alu",
         "achieved": achieved,
         "peak": peak,
@@ -144,6 +221,11 @@ def main():
     ncell = info["grid"][0] * info["grid"][1] * info["grid"][2]
     p2g_bytes = wl.n * 6 * real + 3 * ncell * real
     p2g_gbs = p2g_bytes / (stages["p2g"] * 1e-3) / 1e9 if stages["p2g"] > 0 else None
+    per_stage = stage_roofline(stages, wl.n, ncell, info["P"], real, pairs, peak)
+    serving = None
+    if args.serve_requests > 0:
+        serving = serving_leg(args.serve_requests)
+        log("serving:", json.dumps(serving))
     s_ms = sorted(step_ms)
     p50 = s_ms[len(s_ms) // 2]
     p99 = s_ms[min(len(s_ms) - 1, int(math.ceil(0.99 * len(s_ms))) - 1)]
@@ -167,8 +249,9 @@ def main():
                                              "x".join(str(m) for m in info["grid"]), info["P"], precision),
             "n": wl.n, "tol": wl.tol, "grid": list(info["grid"]), "P": info["P"], "xi": info["xi"],
             "r_c": info["r_c"], "rel_err_sampled": rel_err, "stage_ms": stages,
-            "p2g_GBs": p2g_gbs, "p50_ms": p50, "p99_ms": p99,
+            "p2g_GBs": p2g_gbs, "p50_ms": p50, "p99_ms": p99, "stage_roofline": per_stage,
         },
+        "serving": serving,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -16,6 +16,12 @@ Conventions (each a reading of the paper, recorded in the design notes):
   alpha = 2 m^2 / (P h)^2 with shape parameter m (the classic Gaussian window
   the paper cites in Sec. 2.2); its Fourier transform is taken untruncated,
   w0^(k) = sqrt(pi/alpha) exp(-k^2 / (4 alpha));
+* or the truncated Kaiser-Bessel window of Sec. 2.2 (``window="kb"``):
+  w0(d) = I0(beta sqrt(1 - d^2/a^2)) / I0(beta) for |d| < a, a = P h / 2,
+  beta = 2.5 P (the shape parameter ``m`` is then ignored), with the closed-form
+  transform of the truncated window (the KB transform pair),
+  w0^(k) = 2a sinh(sqrt(beta^2 - (k a)^2)) / (sqrt(beta^2 - (k a)^2) I0(beta))
+  (sin and sqrt((k a)^2 - beta^2) when k a > beta);
 * P2G without h^3 (eq. p2g), G2P with h^3 (eq. g2p), forward DFT unnormalised,
   inverse DFT with 1/prod(M) (numpy's convention), eq. (sca) in between;
 * the k = 0 mode and the Nyquist planes (index M/2) are set to zero.
@@ -25,11 +31,26 @@ from __future__ import annotations
 import math
 
 import numpy as np
+from scipy.special import i0 as _i0
 
 from . import real_space, self_term, wrap
 
 
-def stencil_1d(y, Ld, Md, P, m):
+def window_1d(dist, h, P, m, window="gaussian"):
+    """The 1D window w0 at distances ``dist`` (open support |dist| < P h / 2)."""
+    a = P * h / 2
+    inside = np.abs(dist) < a
+    if window == "kb":
+        beta = 2.5 * P
+        z = np.clip(1.0 - (dist / a) ** 2, 0.0, None)
+        w = _i0(beta * np.sqrt(z)) / _i0(beta)
+    else:
+        alpha = 2.0 * m * m / (P * h) ** 2
+        w = np.exp(-alpha * dist * dist)
+    return np.where(inside, w, 0.0)
+
+
+def stencil_1d(y, Ld, Md, P, m, window="gaussian"):
     """Grid indices (n, P) and window weights (n, P) of the P-point stencil along one axis."""
     h = Ld / Md
     c = np.floor(y / h)
@@ -37,20 +58,26 @@ def stencil_1d(y, Ld, Md, P, m):
     j = np.arange(P, dtype=np.float64)
     idx = (c[:, None].astype(np.int64) - (P // 2 - 1) + np.arange(P, dtype=np.int64)[None, :]) % Md
     dist = (j[None, :] - (P / 2 - 1) - t[:, None]) * h  # g_l - y
-    alpha = 2.0 * m * m / (P * h) ** 2
-    w = np.exp(-alpha * dist * dist)
-    w = np.where(np.abs(dist) < P * h / 2, w, 0.0)
-    return idx, w
+    return idx, window_1d(dist, h, P, m, window)
 
 
-def window_hat_1d(k, Ld, Md, P, m):
-    """Fourier transform of the (untruncated) 1D Gaussian window at wave numbers k."""
+def window_hat_1d(k, Ld, Md, P, m, window="gaussian"):
+    """Fourier transform of the 1D window at wave numbers k (Gaussian: untruncated)."""
     h = Ld / Md
+    if window == "kb":
+        a = P * h / 2
+        beta = 2.5 * P
+        q = beta * beta - (k * a) ** 2
+        sq = np.sqrt(np.abs(q))
+        with np.errstate(invalid="ignore", divide="ignore"):
+            hyp = np.where(q > 0, np.sinh(sq) / np.where(sq > 0, sq, 1.0), np.sin(sq) / np.where(sq > 0, sq, 1.0))
+        hyp = np.where(sq == 0, 1.0, hyp)
+        return 2.0 * a * hyp / _i0(beta)
     alpha = 2.0 * m * m / (P * h) ** 2
     return math.sqrt(math.pi / alpha) * np.exp(-k * k / (4.0 * alpha))
 
 
-def p2g(x, f, L, M, P, m, chunk=4096):
+def p2g(x, f, L, M, P, m, chunk=4096, window="gaussian"):
     """eq. (p2g): phi(g_l) = sum_j w(g_l - y_j + p) f_j.  Returns (3, M1, M2, M3)."""
     x = wrap(np.asarray(x, dtype=np.float64), L)
     f = np.asarray(f, dtype=np.float64)
@@ -59,9 +86,9 @@ def p2g(x, f, L, M, P, m, chunk=4096):
     n = x.shape[1]
     for s in range(0, n, chunk):
         e = min(n, s + chunk)
-        i0, w0 = stencil_1d(x[0, s:e], L[0], M[0], P, m)
-        i1, w1 = stencil_1d(x[1, s:e], L[1], M[1], P, m)
-        i2, w2 = stencil_1d(x[2, s:e], L[2], M[2], P, m)
+        i0, w0 = stencil_1d(x[0, s:e], L[0], M[0], P, m, window)
+        i1, w1 = stencil_1d(x[1, s:e], L[1], M[1], P, m, window)
+        i2, w2 = stencil_1d(x[2, s:e], L[2], M[2], P, m, window)
         flat = (i0[:, :, None, None] * M[1] + i1[:, None, :, None]) * M[2] + i2[:, None, None, :]
         w = w0[:, :, None, None] * w1[:, None, :, None] * w2[:, None, None, :]
         flat = flat.reshape(-1)
@@ -77,7 +104,7 @@ def wave_numbers(L, M):
     return ns, ks
 
 
-def cnv(phihat, L, M, xi, P, m):
+def cnv(phihat, L, M, xi, P, m, window="gaussian"):
     """eq. (sca): vhat(k) = Ghat^F(k) / what(k)^2 phihat(k), Ghat^F from eq. (GFk).
 
     ``phihat``: (3, M1, M2, M3) complex, the unnormalised DFT of the grid.
@@ -91,9 +118,9 @@ def cnv(phihat, L, M, xi, P, m):
     with np.errstate(divide="ignore", invalid="ignore"):
         g = 8.0 * math.pi / (kk * kk) * (1.0 + kk / (4.0 * xi * xi)) * np.exp(-kk / (4.0 * xi * xi))
     what = (
-        window_hat_1d(ks[0], L[0], M[0], P, m)[:, None, None]
-        * window_hat_1d(ks[1], L[1], M[1], P, m)[None, :, None]
-        * window_hat_1d(ks[2], L[2], M[2], P, m)[None, None, :]
+        window_hat_1d(ks[0], L[0], M[0], P, m, window)[:, None, None]
+        * window_hat_1d(ks[1], L[1], M[1], P, m, window)[None, :, None]
+        * window_hat_1d(ks[2], L[2], M[2], P, m, window)[None, None, :]
     )
     scale = g / (what * what)
     bad = kk == 0.0
@@ -114,7 +141,7 @@ def cnv(phihat, L, M, xi, P, m):
     )
 
 
-def g2p(v, x, L, M, P, m, chunk=4096):
+def g2p(v, x, L, M, P, m, chunk=4096, window="gaussian"):
     """eq. (g2p): u(x_i) = h1 h2 h3 sum_l w(x_i - g_l + p) v(g_l).  Returns (3, n)."""
     x = wrap(np.asarray(x, dtype=np.float64), L)
     M = [int(q) for q in M]
@@ -124,9 +151,9 @@ def g2p(v, x, L, M, P, m, chunk=4096):
     u = np.zeros((3, n), dtype=np.float64)
     for s in range(0, n, chunk):
         e = min(n, s + chunk)
-        i0, w0 = stencil_1d(x[0, s:e], L[0], M[0], P, m)
-        i1, w1 = stencil_1d(x[1, s:e], L[1], M[1], P, m)
-        i2, w2 = stencil_1d(x[2, s:e], L[2], M[2], P, m)
+        i0, w0 = stencil_1d(x[0, s:e], L[0], M[0], P, m, window)
+        i1, w1 = stencil_1d(x[1, s:e], L[1], M[1], P, m, window)
+        i2, w2 = stencil_1d(x[2, s:e], L[2], M[2], P, m, window)
         flat = (i0[:, :, None, None] * M[1] + i1[:, None, :, None]) * M[2] + i2[:, None, None, :]
         w = w0[:, :, None, None] * w1[:, None, :, None] * w2[:, None, None, :]
         for d in range(3):
@@ -134,27 +161,27 @@ def g2p(v, x, L, M, P, m, chunk=4096):
     return u
 
 
-def far_grid(x, f, L, M, xi, P, m):
+def far_grid(x, f, L, M, xi, P, m, window="gaussian"):
     """P2G -> FFT -> CNV -> IFFT: the real grid v(g_l) that G2P interpolates."""
-    phi = p2g(x, f, L, M, P, m)
+    phi = p2g(x, f, L, M, P, m, window=window)
     phihat = np.fft.fftn(phi, axes=(1, 2, 3))
-    vhat = cnv(phihat, L, M, xi, P, m)
+    vhat = cnv(phihat, L, M, xi, P, m, window)
     return np.real(np.fft.ifftn(vhat, axes=(1, 2, 3)))
 
 
-def far_field(x, f, L, M, xi, P, m):
+def far_field(x, f, L, M, xi, P, m, window="gaussian"):
     """u^F_h at every particle: G2P(IFFT(CNV(FFT(P2G(f))))).  Returns (3, n)."""
-    v = far_grid(x, f, L, M, xi, P, m)
-    return g2p(v, x, L, M, P, m)
+    v = far_grid(x, f, L, M, xi, P, m, window)
+    return g2p(v, x, L, M, P, m, window=window)
 
 
-def spectral_ewald(x, f, L, M, xi, r_c, P, m, parts=False):
+def spectral_ewald(x, f, L, M, xi, r_c, P, m, parts=False, window="gaussian"):
     """Algorithm "se": u_h = u^N + u^F_h, plus the self term -(4 xi/sqrt(pi)) f.
 
     Returns (3, n), or (total, near, far, self) when ``parts``.
     """
     un = real_space(x, f, L, xi, r_c)
-    uf = far_field(x, f, L, M, xi, P, m)
+    uf = far_field(x, f, L, M, xi, P, m, window)
     us = self_term(f, xi)
     tot = un + uf + us
     if parts:

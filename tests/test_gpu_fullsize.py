@@ -55,3 +55,27 @@ def test_c2_configured_window_error_is_reported(c2):
     err = oracle.rel_err(u[:, tgt], oracle.ewald_sum(x, f, wl.box, targets=tgt))
     print("c2 at P=12: sampled relative error %.3e (window model %.2e)" % (err, plan.info["err_window"]))
     assert err < 10 * plan.info["err_window"]
+
+
+@pytest.mark.parametrize("name", ["c3", "c4", "H"])
+def test_fp32_configs_full_size(name):
+    """FP32 bulk at full size: sampled error within tol, and against the FP64 GPU path."""
+    import paper_2606_19059_amd as E
+
+    wl = W.WORKLOADS[name]
+    x, f = wl.make()
+    X = torch.from_numpy(x).to("cuda")
+    F = torch.from_numpy(f).to("cuda")
+    p32 = E.Plan(wl.box, wl.tol, grid=wl.grid, n_max=wl.n, precision="fp32")
+    u32 = p32.eval(X, F).cpu().numpy()
+    tgt = W.sample_targets(wl.n, 12, seed=100 + int(name[1:]) if name[1:].isdigit() else 111)
+    ref = oracle.ewald_sum(x, f, wl.box, targets=tgt)
+    err = oracle.rel_err(u32[:, tgt], ref)
+    # the FP64 path at a tighter tolerance on the same grid, all N
+    p64 = E.Plan(wl.box, min(wl.tol, 1e-8), grid=wl.grid, n_max=wl.n, precision="fp64")
+    u64 = p64.eval(X, F).cpu().numpy()
+    err_full = oracle.rel_err(u32, u64)
+    print("%s: fp32 P=%d sampled err %.3e, full-N err vs FP64 path %.3e (tol %g)"
+          % (name, p32.info["P"], err, err_full, wl.tol))
+    assert err <= wl.tol
+    assert err_full <= wl.tol

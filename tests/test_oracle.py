@@ -262,3 +262,26 @@ def test_spectral_total_matches_classical_ewald():
     P = 12
     u = S.spectral_ewald(x, f, L, (32, 32, 32), xi, rc, P, 0.94 * math.sqrt(math.pi * P))
     assert oracle.rel_err(u, ue) < 3e-7
+
+
+def test_kaiser_bessel_transform_matches_quadrature():
+    """The closed-form transform of the truncated KB window (Sec. 2.2) against direct quadrature."""
+    from scipy.integrate import quad
+
+    h, P = 1.0 / 32, 8
+    a = P * h / 2
+    for k in (0.0, 17.0, 150.0, 2 * math.pi * 15):
+        num, _ = quad(lambda d: float(S.window_1d(np.array([d]), h, P, 0, "kb")[0]) * math.cos(k * d), -a, a,
+                      epsabs=1e-14, epsrel=1e-12, limit=400)
+        ana = float(S.window_hat_1d(np.array([k]), 1.0, 32, P, 0, "kb")[0])
+        assert abs(num - ana) < 1e-10 * abs(ana)
+
+
+def test_kaiser_bessel_far_field_converges():
+    L = np.array([1.0, 1.0, 1.0])
+    x, f = W.particles(200, L, seed=1)
+    xi = 11.444
+    ref = oracle.recip_space(x, f, L, xi, 12 * 60)
+    errs = [oracle.rel_err(S.far_field(x, f, L, (32, 32, 32), xi, P, 0, window="kb"), ref) for P in (4, 6, 8)]
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 1e-6
