@@ -58,7 +58,9 @@ enum {
                             self terms, final sum in FP64 */
     EWALD_FLAG_P2P_FP64_ACC = 1 << 8, /* FP32 bulk: accumulate each particle's near-field
                                          sum in FP64 (automatic when tol < 1e-7) */
-    EWALD_FLAG_STAGE_TIMERS = 1 << 9  /* record per-stage HIP events (see ewald_stage_ms) */
+    EWALD_FLAG_STAGE_TIMERS = 1 << 9, /* record per-stage HIP events (see ewald_stage_ms) */
+    EWALD_FLAG_WINDOW_KB = 1 << 10    /* truncated Kaiser-Bessel window (Sec. 2.2) instead of the
+                                         Gaussian: w0(d) = I0(beta sqrt(1 - (2d/(P h))^2)) / I0(beta) */
 };
 
 /*
@@ -78,7 +80,8 @@ typedef struct {
     int32_t precision;   /* EWALD_FP64 or EWALD_FP32_BULK, OR'd with EWALD_FLAG_* */
     int32_t reserved;    /* must be 0 */
     int64_t n_max;       /* largest n this plan will evaluate (sizes workspace queries) */
-    double window_shape; /* Gaussian shape m (w0(d) = exp(-2 m^2 d^2 / (P h)^2)); <= 0: derive */
+    double window_shape; /* Gaussian: shape m, w0(d) = exp(-2 m^2 d^2 / (P h)^2); Kaiser-Bessel:
+                            beta / P; <= 0: derive */
 } ewald_params;
 
 /* Everything a plan resolved (returned by ewald_plan_get_info). */
@@ -87,7 +90,7 @@ typedef struct {
     double h[3];              /* grid spacing L_d / M_d */
     double err_near;          /* predicted near-field RMS error term E^N (eq. (ese)) */
     double err_far;           /* predicted Fourier truncation term E^F (eq. (ese)) */
-    double err_window;        /* predicted window error (Gaussian-window model) */
+    double err_window;        /* predicted window error (window model of the plan's window) */
     int32_t tile;             /* P2P cell edge, in grid cells */
     int32_t n_tiles[3];       /* P2P cells per dimension */
     int32_t stencil[3];       /* P2P neighbour half-width, in cells */

@@ -18,7 +18,7 @@ Conventions (each a reading of the paper, recorded in the design notes):
   w0^(k) = sqrt(pi/alpha) exp(-k^2 / (4 alpha));
 * or the truncated Kaiser-Bessel window of Sec. 2.2 (``window="kb"``):
   w0(d) = I0(beta sqrt(1 - d^2/a^2)) / I0(beta) for |d| < a, a = P h / 2,
-  beta = 2.5 P (the shape parameter ``m`` is then ignored), with the closed-form
+  beta = m P (m = 2.5 when not given, the paper's choice), with the closed-form
   transform of the truncated window (the KB transform pair),
   w0^(k) = 2a sinh(sqrt(beta^2 - (k a)^2)) / (sqrt(beta^2 - (k a)^2) I0(beta))
   (sin and sqrt((k a)^2 - beta^2) when k a > beta);
@@ -41,7 +41,7 @@ def window_1d(dist, h, P, m, window="gaussian"):
     a = P * h / 2
     inside = np.abs(dist) < a
     if window == "kb":
-        beta = 2.5 * P
+        beta = (m if m else 2.5) * P
         z = np.clip(1.0 - (dist / a) ** 2, 0.0, None)
         w = _i0(beta * np.sqrt(z)) / _i0(beta)
     else:
@@ -66,7 +66,7 @@ def window_hat_1d(k, Ld, Md, P, m, window="gaussian"):
     h = Ld / Md
     if window == "kb":
         a = P * h / 2
-        beta = 2.5 * P
+        beta = (m if m else 2.5) * P
         q = beta * beta - (k * a) ** 2
         sq = np.sqrt(np.abs(q))
         with np.errstate(invalid="ignore", divide="ignore"):

@@ -24,6 +24,7 @@ EWALD_FP64 = 0
 EWALD_FP32_BULK = 1
 EWALD_FLAG_P2P_FP64_ACC = 1 << 8
 EWALD_FLAG_STAGE_TIMERS = 1 << 9
+EWALD_FLAG_WINDOW_KB = 1 << 10
 
 STAGES = ("sort", "p2p", "p2g", "fgc", "g2p", "total")
 
@@ -145,7 +146,7 @@ def _check_particles(x, f):
 
 
 def make_params(box, tol, xi=None, r_c=None, grid=None, P=None, precision="fp64", n_max=1 << 20,
-                window_shape=None, p2p_fp64_acc=False, timers=False):
+                window_shape=None, p2p_fp64_acc=False, timers=False, window="gaussian"):
     """The ewald_params struct for these arguments (None = derive from tol)."""
     p = Params()
     for d in range(3):
@@ -156,8 +157,10 @@ def make_params(box, tol, xi=None, r_c=None, grid=None, P=None, precision="fp64"
     p.P = int(P) if P else 0
     p.tol = float(tol)
     mode = {"fp64": EWALD_FP64, "fp32": EWALD_FP32_BULK}[precision]
+    if window not in ("gaussian", "kb"):
+        raise ValueError("window must be 'gaussian' or 'kb'")
     p.precision = mode | (EWALD_FLAG_P2P_FP64_ACC if p2p_fp64_acc else 0) | (
-        EWALD_FLAG_STAGE_TIMERS if timers else 0)
+        EWALD_FLAG_STAGE_TIMERS if timers else 0) | (EWALD_FLAG_WINDOW_KB if window == "kb" else 0)
     p.reserved = 0
     p.n_max = int(n_max)
     p.window_shape = float(window_shape) if window_shape else 0.0
@@ -172,6 +175,7 @@ def _info_dict(info, precision):
         "h": tuple(info.h), "err_near": info.err_near, "err_far": info.err_far,
         "err_window": info.err_window, "tile": info.tile, "n_tiles": tuple(info.n_tiles),
         "stencil": tuple(info.stencil), "workspace_bytes": info.workspace_bytes,
+        "window": "kb" if q.precision & EWALD_FLAG_WINDOW_KB else "gaussian",
     }
 
 
@@ -192,9 +196,10 @@ class Plan:
     """
 
     def __init__(self, box, tol, xi=None, r_c=None, grid=None, P=None, precision="fp64", n_max=1 << 20,
-                 window_shape=None, p2p_fp64_acc=False, timers=False):
+                 window_shape=None, p2p_fp64_acc=False, timers=False, window="gaussian"):
         lib = load()
-        p = make_params(box, tol, xi, r_c, grid, P, precision, n_max, window_shape, p2p_fp64_acc, timers)
+        p = make_params(box, tol, xi, r_c, grid, P, precision, n_max, window_shape, p2p_fp64_acc, timers,
+                        window)
         h = ctypes.c_void_p()
         _check(lib.ewald_plan_create(ctypes.byref(p), ctypes.byref(h)))
         self._h = h

@@ -13,6 +13,7 @@
 
 #include "internal.h"
 #include "screening.h"
+#include "window.h"
 
 namespace ewald {
 int p2g_max_runs();
@@ -134,6 +135,53 @@ double best_shape(int P, double h, double xi)
     return best_m;
 }
 
+// Kaiser-Bessel window (Sec. 2.2), with beta tuned per support: relative far-field error
+// (log10) and the best beta/P at P = 6..16, measured against the direct Fourier sum for
+// uniform particles at four values of xi h (the window error depends on xi h through the
+// band the deconvolution amplifies).  Rows whose error stops falling with P have reached
+// that grid's own Fourier truncation.  Interpolated linearly in xi h (clamped).
+const double kKbXh[4] = {0.22, 0.28, 0.33, 0.40};
+const int kKbP[6] = {6, 8, 10, 12, 14, 16};
+const double kKbLogErr[4][6] = {{-6.20, -8.37, -10.40, -12.27, -13.78, -14.31},
+                                {-5.90, -7.84, -9.60, -11.16, -12.48, -13.41},
+                                {-5.68, -7.38, -8.75, -9.74, -10.26, -10.31},
+                                {-5.25, -6.51, -7.14, -7.22, -7.22, -7.22}};
+const double kKbBetaOverP[4][6] = {{2.8, 2.7, 2.6, 2.6, 2.4, 2.4},
+                                   {2.7, 2.5, 2.4, 2.3, 2.2, 2.1},
+                                   {2.5, 2.4, 2.2, 2.1, 1.9, 1.8},
+                                   {2.3, 2.1, 1.9, 1.7, 1.6, 1.6}};
+
+double kb_interp(const double tab[4][6], int P, double xh)
+{
+    int pi = 0;
+    while (pi < 5 && kKbP[pi] < P) ++pi;
+    xh = std::min(std::max(xh, kKbXh[0]), kKbXh[3]);
+    int r = 0;
+    while (r < 2 && xh > kKbXh[r + 1]) ++r;
+    const double f = (xh - kKbXh[r]) / (kKbXh[r + 1] - kKbXh[r]);
+    return (1.0 - f) * tab[r][pi] + f * tab[r + 1][pi];
+}
+
+double err_window_kb(int P, double h, double xi) { return std::pow(10.0, kb_interp(kKbLogErr, P, h * xi)); }
+double kb_beta_over_p(int P, double h, double xi) { return kb_interp(kKbBetaOverP, P, h * xi); }
+
+// 1D Kaiser-Bessel window at distance u (in grid spacings), support |u| < P/2, and its
+// Fourier transform at k (a = P h / 2): 2a sinh(sqrt(beta^2 - (ka)^2)) / (sqrt(.) I0(beta)).
+double kb_w(double u, int P, double beta)
+{
+    const double z = 1.0 - std::pow(2.0 * u / P, 2);
+    return std::cyl_bessel_i(0.0, beta * std::sqrt(std::max(z, 0.0))) / std::cyl_bessel_i(0.0, beta);
+}
+
+double kb_hat(double k, double a, double beta)
+{
+    const double q = beta * beta - (k * a) * (k * a);
+    const double sq = std::sqrt(std::fabs(q));
+    double hyp = 1.0;
+    if (sq > 0) hyp = (q > 0) ? std::sinh(sq) / sq : std::sin(sq) / sq;
+    return 2.0 * a * hyp / std::cyl_bessel_i(0.0, beta);
+}
+
 int64_t align256(int64_t v) { return (v + 255) & ~(int64_t)255; }
 
 }  // namespace
@@ -185,7 +233,7 @@ int validate_and_resolve(const ewald_params* in, Plan* pl)
     const int mode = p.precision & 0xff;
     if (mode != EWALD_FP64 && mode != EWALD_FP32_BULK)
         return fail(EWALD_EINVAL, "unknown precision mode %d", mode);
-    if (p.precision & ~(0xff | EWALD_FLAG_P2P_FP64_ACC | EWALD_FLAG_STAGE_TIMERS))
+    if (p.precision & ~(0xff | EWALD_FLAG_P2P_FP64_ACC | EWALD_FLAG_STAGE_TIMERS | EWALD_FLAG_WINDOW_KB))
         return fail(EWALD_EINVAL, "unknown precision flags 0x%x", p.precision);
     if (mode == EWALD_FP32_BULK && p.tol < 1e-7)
         return fail(EWALD_EUNSUPPORTED, "tol = %g below 1e-7 needs the FP64 mode", p.tol);
@@ -242,25 +290,28 @@ int validate_and_resolve(const ewald_params* in, Plan* pl)
     if (p.r_c < hmin) return fail(EWALD_EINVAL, "r_c = %g below the grid spacing %g", p.r_c, hmin);
 
     // window support and shape
+    const bool kb = (p.precision & EWALD_FLAG_WINDOW_KB) != 0;
+    if (kb && p.P > 0 && p.P < 6) return fail(EWALD_EINVAL, "P = %d: the Kaiser-Bessel window needs P >= 6", p.P);
     if (!(p.P > 0)) {
         p.P = 16;
-        for (int P = 4; P <= 16; P += 2) {
-            const double m = best_shape(P, h, p.xi);
-            if (err_window(P, m, h, p.xi) <= third) {
+        for (int P = kb ? 6 : 4; P <= 16; P += 2) {
+            const double e = kb ? err_window_kb(P, h, p.xi) : err_window(P, best_shape(P, h, p.xi), h, p.xi);
+            if (e <= third) {
                 p.P = P;
                 break;
             }
         }
     }
-    if (!(p.window_shape > 0)) p.window_shape = best_shape(p.P, h, p.xi);
+    if (!(p.window_shape > 0)) p.window_shape = kb ? kb_beta_over_p(p.P, h, p.xi) : best_shape(p.P, h, p.xi);
 
     pl->p = p;
     pl->mode = mode;
     pl->fp64acc = (p.precision & EWALD_FLAG_P2P_FP64_ACC) || p.tol < 1e-7;
     pl->timers = (p.precision & EWALD_FLAG_STAGE_TIMERS) != 0;
     pl->P = p.P;
+    pl->window_kb = kb;
     pl->m = p.window_shape;
-    pl->beta = 2.0 * p.window_shape * p.window_shape / ((double)p.P * p.P);
+    pl->beta = kb ? p.window_shape * p.P : 2.0 * p.window_shape * p.window_shape / ((double)p.P * p.P);
     pl->xi = p.xi;
     pl->rc = p.r_c;
 
@@ -299,7 +350,7 @@ int validate_and_resolve(const ewald_params* in, Plan* pl)
     }
     info.err_near = err_near(p.xi, p.r_c);
     info.err_far = err_far(p.xi, h);
-    info.err_window = err_window(p.P, p.window_shape, h, p.xi);
+    info.err_window = kb ? err_window_kb(p.P, h, p.xi) : err_window(p.P, p.window_shape, h, p.xi);
     info.tile = B;
     info.workspace_bytes = layout_work(*pl, p.n_max, nullptr, nullptr);
     return EWALD_OK;
@@ -318,14 +369,63 @@ int build_tables(Plan* pl)
     for (int d = 0; d < 3; ++d) {
         cnv_off[d] = cnv.size();
         const double alpha = 2.0 * pl->m * pl->m / std::pow(pl->P * g.h[d], 2);
+        const double a = pl->P * g.h[d] / 2.0;
         for (int k = 0; k < lens[d]; ++k) {
             int ks = k;
             if (d < 2) ks = (k < g.M[d] / 2) ? k : k - g.M[d];
             const bool nyq = (d < 2) && (k == g.M[d] / 2);
-            const double kk = std::pow(2.0 * M_PI * ks / g.L[d], 2);
-            double v = nyq ? 0.0 : (alpha / M_PI) * std::exp(kk * (1.0 / (2.0 * alpha) - 1.0 / (4.0 * pl->xi * pl->xi)));
+            const double kd = 2.0 * M_PI * ks / g.L[d];
+            const double kk = kd * kd;
+            double v = 0.0;
+            if (!nyq) {
+                if (pl->window_kb) {
+                    const double wh = kb_hat(kd, a, pl->beta);
+                    v = std::exp(-kk / (4.0 * pl->xi * pl->xi)) / (wh * wh);
+                } else {
+                    v = (alpha / M_PI) * std::exp(kk * (1.0 / (2.0 * alpha) - 1.0 / (4.0 * pl->xi * pl->xi)));
+                }
+            }
             if (d == 0) v *= scale;
             cnv.push_back(v);
+        }
+    }
+    // Kaiser-Bessel weights: per stencil offset j, the weight as a polynomial of degree kKbDeg in
+    // s = 2t - 1 (t the particle's fraction in its cell): Chebyshev interpolation at 32 points
+    // (the weight is analytic in t), truncated, converted to monomials.
+    std::vector<double> kb64;
+    if (pl->window_kb) {
+        const int P = pl->P, NC = 32, D = kKbDeg;
+        for (int j = 0; j < P; ++j) {
+            std::vector<double> val(NC), cheb(NC, 0.0);
+            for (int q = 0; q < NC; ++q) {
+                const double sq = std::cos(M_PI * (q + 0.5) / NC);
+                const double t = 0.5 * (sq + 1.0);
+                val[q] = kb_w(j - (P / 2 - 1) - t, P, pl->beta);
+            }
+            for (int c = 0; c < NC; ++c) {
+                double acc = 0.0;
+                for (int q = 0; q < NC; ++q) acc += val[q] * std::cos(M_PI * c * (q + 0.5) / NC);
+                cheb[c] = (c ? 2.0 : 1.0) * acc / NC;
+            }
+            // Chebyshev -> monomial: T_0 = 1, T_1 = s, T_{c+1} = 2 s T_c - T_{c-1}
+            std::vector<double> mono(D + 1, 0.0), tm1(D + 1, 0.0), t0(D + 1, 0.0), t1(D + 1, 0.0);
+            t0[0] = 1.0;
+            for (int c = 0; c <= D; ++c) {
+                const std::vector<double>& tc = (c == 0) ? t0 : t1;
+                for (int e = 0; e <= D; ++e) mono[e] += cheb[c] * tc[e];
+                if (c == 0) {
+                    t1.assign(D + 1, 0.0);
+                    t1[1] = 1.0;
+                    tm1 = t0;
+                } else {
+                    std::vector<double> nx(D + 1, 0.0);
+                    for (int e = 0; e < D; ++e) nx[e + 1] += 2.0 * t1[e];
+                    for (int e = 0; e <= D; ++e) nx[e] -= tm1[e];
+                    tm1 = t1;
+                    t1 = nx;
+                }
+            }
+            kb64.insert(kb64.end(), mono.begin(), mono.end());
         }
     }
     // twiddles e^{-2 pi i j / n} for n = M1, M2, M3/2, M3
@@ -347,17 +447,25 @@ int build_tables(Plan* pl)
     const size_t b_cnv = align256(cnv.size() * 8);
     const size_t b_tw64 = align256(tw64.size() * 8);
     const size_t b_tw32 = align256(tw32.size() * 4);
+    std::vector<float> kb32(kb64.begin(), kb64.end());
+    const size_t b_kb64 = align256(kb64.size() * 8 + 8);
+    const size_t b_kb32 = align256(kb32.size() * 4 + 4);
     char* d = nullptr;
-    hipError_t e = hipMalloc((void**)&d, b_cnv + b_tw64 + b_tw32);
+    hipError_t e = hipMalloc((void**)&d, b_cnv + b_tw64 + b_tw32 + b_kb64 + b_kb32);
     if (e != hipSuccess) return fail(EWALD_ENOMEM, "plan tables: %s", hipGetErrorString(e));
     pl->d_tables = d;
     e = hipMemcpy(d, cnv.data(), cnv.size() * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d + b_cnv, tw64.data(), tw64.size() * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d + b_cnv + b_tw64, tw32.data(), tw32.size() * 4, hipMemcpyHostToDevice);
+    char* dkb = d + b_cnv + b_tw64 + b_tw32;
+    if (e == hipSuccess && !kb64.empty()) e = hipMemcpy(dkb, kb64.data(), kb64.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess && !kb32.empty()) e = hipMemcpy(dkb + b_kb64, kb32.data(), kb32.size() * 4, hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "plan table upload");
     for (int k = 0; k < 3; ++k) pl->d_cnv[k] = (double*)d + cnv_off[k];
     pl->d_tw64 = d + b_cnv;
     pl->d_tw32 = d + b_cnv + b_tw64;
+    pl->d_kb64 = pl->window_kb ? (double*)dkb : nullptr;
+    pl->d_kb32 = pl->window_kb ? (float*)(dkb + b_kb64) : nullptr;
     return EWALD_OK;
 }
 

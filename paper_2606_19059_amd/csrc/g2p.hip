@@ -53,10 +53,7 @@ __global__ __launch_bounds__(64) void k_g2p(int n, const typename RecView<T>::Re
         if (lane < 3 * P) {
             const int d = lane / P, j = lane - d * P;
             const T td = (d == 0) ? t[0] : (d == 1 ? t[1] : t[2]);
-            const T uu = (T)(j - (P / 2 - 1)) - td;
-            T wv = exp(-wa.beta * uu * uu);
-            if (j == P - 1 && td == (T)0) wv = (T)0;  // open support
-            sw[d][j] = wv;
+            sw[d][j] = window_weight_one<T, P>(j, td, wa);
         }
         __syncthreads();
         T a0 = 0, a1 = 0, a2 = 0;
@@ -100,14 +97,6 @@ __global__ __launch_bounds__(64) void k_g2p(int n, const typename RecView<T>::Re
     }
 }
 
-template <typename T>
-WinArgs<T> win_args(const Plan& pl)
-{
-    WinArgs<T> wa;
-    wa.beta = (T)pl.beta;
-    for (int j = 0; j < kMaxP; ++j) wa.ratio[j] = (T)exp(-pl.beta * (2.0 * j + 1.0));
-    return wa;
-}
 
 template <typename T, int P>
 hipError_t launch_g2p_t(const Plan& pl, const Work& w, int n, const double* f, double* u, double* un,
@@ -115,7 +104,7 @@ hipError_t launch_g2p_t(const Plan& pl, const Work& w, int n, const double* f, d
 {
     const double self_coef = 4.0 * pl.xi / sqrt(M_PI);
     hipLaunchKernelGGL((k_g2p<T, P>), dim3((n + kG2PPerWave - 1) / kG2PPerWave), dim3(kWave), 0, s, n,
-                       (const typename RecView<T>::Rec*)w.rec, (const T*)w.grid, pl.g, win_args<T>(pl),
+                       (const typename RecView<T>::Rec*)w.rec, (const T*)w.grid, pl.g, make_win_args<T>(pl),
                        self_coef, w.u_near, f, u, un, uf);
     return hipGetLastError();
 }

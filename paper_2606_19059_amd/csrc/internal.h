@@ -48,8 +48,9 @@ struct Plan {
     ewald_plan_info info;  // what get_info returns
     Geometry g;
     int P;                 // window support
-    double m;              // Gaussian shape
-    double beta;           // 2 m^2 / P^2: w0 = exp(-beta u^2), u = distance / h
+    bool window_kb;        // Kaiser-Bessel window (else Gaussian)
+    double m;              // Gaussian shape m, or Kaiser-Bessel beta / P
+    double beta;           // Gaussian: 2 m^2 / P^2 (w0 = exp(-beta u^2), u = distance / h); KB: beta
     double xi, rc;
     int mode;              // EWALD_FP64 or EWALD_FP32_BULK
     bool fp64acc;          // FP32 bulk: FP64 near-field accumulation
@@ -60,6 +61,8 @@ struct Plan {
     double* d_cnv[3];      // per-axis CNV factors E_d[k] (FP64), lengths M1, M2, M3/2
     void* d_tw64;          // twiddles e^{-2 pi i j / n} (double2), per FFT length
     void* d_tw32;          // same in float2
+    double* d_kb64;        // Kaiser-Bessel weight polynomials, P x (kKbDeg + 1) (KB plans only)
+    float* d_kb32;
     int tw_off[4];         // element offsets: axis0 (M1), axis1 (M2), half z (M3/2), full z (M3)
     hipEvent_t ev[kNumStages + 1];
     float stage_ms[kNumStages];

@@ -182,14 +182,6 @@ __global__ __launch_bounds__(kWaves * 64) void k_p2g_sweep(const typename RecVie
     }
 }
 
-template <typename T>
-WinArgs<T> win_args(const Plan& pl)
-{
-    WinArgs<T> wa;
-    wa.beta = (T)pl.beta;
-    for (int j = 0; j < kMaxP; ++j) wa.ratio[j] = (T)exp(-pl.beta * (2.0 * j + 1.0));
-    return wa;
-}
 
 template <typename TG, int P>
 hipError_t launch_p2g_t(const Plan& pl, const Work& w, hipStream_t s)
@@ -203,7 +195,7 @@ hipError_t launch_p2g_t(const Plan& pl, const Work& w, hipStream_t s)
     const int nseg = (g.M[0] + seg - 1) / seg;
     const int blocks = nseg * npy * npz;
     hipLaunchKernelGGL((k_p2g_sweep<double, TG, P>), dim3(blocks), dim3(kWaves * kWave), 0, s, (const Rec64*)w.rec,
-                       w.start, g, win_args<double>(pl), seg, npy, npz, (TG*)w.grid);
+                       w.start, g, make_win_args<double>(pl), seg, npy, npz, (TG*)w.grid);
     return hipGetLastError();
 }
 

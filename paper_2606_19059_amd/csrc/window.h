@@ -1,19 +1,34 @@
 // Gaussian window weights and sorted-record accessors shared by P2G and G2P.
 #pragma once
 
+#include <cmath>
+
 #include "internal.h"
 
 namespace ewald {
 
 constexpr int kMaxP = 16;
+constexpr int kKbDeg = 14;  // degree of the per-offset Kaiser-Bessel weight polynomials
 
-// Per-plan window constants for one precision: w0(u) = exp(-beta u^2) with u the
+// Per-plan window constants for one precision.  Gaussian: w0(u) = exp(-beta u^2) with u the
 // distance to the particle in grid spacings, and ratio[j] = exp(-beta (2j + 1)).
+// Kaiser-Bessel (kb != nullptr): kb[j * (kKbDeg + 1) + k] are the monomial coefficients, in
+// s = 2t - 1, of the weight of stencil offset j as a function of the fraction t in [0, 1).
 template <typename T>
 struct WinArgs {
     T beta;
     T ratio[kMaxP];
+    const T* kb;
 };
+
+template <typename T>
+__device__ inline T kb_weight(const T* __restrict__ c, T s)
+{
+    T q = c[kKbDeg];
+#pragma unroll
+    for (int k = kKbDeg - 1; k >= 0; --k) q = fma(q, s, c[k]);
+    return q;
+}
 
 // The P weights of the stencil of a particle with fraction t = y/h - floor(y/h):
 // w[j] = w0(j - (P/2 - 1) - t), j = 0..P-1 (grid points floor(y/h) - P/2 + 1 + j).
@@ -24,12 +39,45 @@ struct WinArgs {
 template <typename T, int P>
 __device__ inline void window_weights(T t, const WinArgs<T>& wa, T* w)
 {
-    const T m0 = (T)(P / 2 - 1) + t;
-    const T E = exp((T)2 * wa.beta * m0);
-    w[0] = exp(-wa.beta * m0 * m0);
+    if (wa.kb) {
+        const T s = (T)2 * t - (T)1;
 #pragma unroll
-    for (int j = 0; j + 1 < P; ++j) w[j + 1] = w[j] * (wa.ratio[j] * E);
+        for (int j = 0; j < P; ++j) w[j] = kb_weight<T>(wa.kb + j * (kKbDeg + 1), s);
+    } else {
+        const T m0 = (T)(P / 2 - 1) + t;
+        const T E = exp((T)2 * wa.beta * m0);
+        w[0] = exp(-wa.beta * m0 * m0);
+#pragma unroll
+        for (int j = 0; j + 1 < P; ++j) w[j + 1] = w[j] * (wa.ratio[j] * E);
+    }
     if (t == (T)0) w[P - 1] = (T)0;
+}
+
+// The weight of one stencil offset j (0 <= j < P).
+template <typename T, int P>
+__device__ inline T window_weight_one(int j, T t, const WinArgs<T>& wa)
+{
+    T wv;
+    if (wa.kb) {
+        wv = kb_weight<T>(wa.kb + j * (kKbDeg + 1), (T)2 * t - (T)1);
+    } else {
+        const T uu = (T)(j - (P / 2 - 1)) - t;
+        wv = exp(-wa.beta * uu * uu);
+    }
+    if (j == P - 1 && t == (T)0) wv = (T)0;  // open support
+    return wv;
+}
+
+// Window constants of a plan in precision T (the KB table lives in the plan's device tables).
+template <typename T>
+inline WinArgs<T> make_win_args(const Plan& pl)
+{
+    WinArgs<T> wa;
+    wa.beta = (T)pl.beta;
+    for (int j = 0; j < kMaxP; ++j) wa.ratio[j] = (T)exp(-pl.beta * (2.0 * j + 1.0));
+    wa.kb = nullptr;
+    if (pl.window_kb) wa.kb = (const T*)(sizeof(T) == 8 ? (const void*)pl.d_kb64 : (const void*)pl.d_kb32);
+    return wa;
 }
 
 __device__ inline int wrapi(int a, int M) { return ((a % M) + M) % M; }

@@ -275,3 +275,37 @@ def test_fp32_rejects_tolerance_below_its_precision():
     with pytest.raises(E.EwaldError) as ei:
         E.Plan((1, 1, 1), 1e-9, grid=(32, 32, 32), n_max=10, precision="fp32")
     assert ei.value.code == E.EWALD_EUNSUPPORTED
+
+
+# ---------------------------------------------------------------- Kaiser-Bessel window
+
+
+@pytest.mark.parametrize("name,n,precision", [("cube32_P8", 2000, "fp64"), ("aniso_P12", 1531, "fp64"),
+                                              ("cube16_P16", 600, "fp64"), ("cube32_P8", 1800, "fp32")])
+def test_kb_stages_match_oracle(name, n, precision):
+    E = _E()
+    box, grid, xi, rc, P, _m = CASES[name]
+    bp = 2.2
+    pl = E.Plan(box, 1e-6, xi=xi, r_c=rc, grid=grid, P=P, window_shape=bp, n_max=n, window="kb",
+                precision=precision)
+    assert pl.info["window"] == "kb"
+    x, f = W.particles(n, box, seed=31)
+    X, F = dev(x), dev(f)
+    g = host(pl.spread(X, F)).astype(np.float64)
+    tol_g, tol_f = (1e-12, 1e-11) if precision == "fp64" else (1e-6, 2e-5)
+    assert maxrel(g, S.p2g(x, f, box, grid, P, bp, window="kb")) < tol_g
+    un, uf = pl.eval_parts(X, F)
+    assert maxrel(host(uf), S.far_field(x, f, box, grid, xi, P, bp, window="kb")) < tol_f
+
+
+@pytest.mark.parametrize("tol", [1e-6, 1e-8, 1e-10])
+def test_kb_meets_tolerance_with_smaller_support(tol):
+    E = _E()
+    x, f = W.particles(1500, (1, 1, 1), seed=7)
+    pk = E.Plan((1, 1, 1), tol, grid=(32, 32, 32), n_max=1500, window="kb")
+    pg = E.Plan((1, 1, 1), tol, grid=(32, 32, 32), n_max=1500)
+    u = host(pk.eval(dev(x), dev(f)))
+    err = oracle.rel_err(u, oracle.ewald_sum(x, f, (1, 1, 1)))
+    print("kb tol %g P %d (gaussian P %d) err %.3e" % (tol, pk.info["P"], pg.info["P"], err))
+    assert err <= tol
+    assert pk.info["P"] < pg.info["P"]
