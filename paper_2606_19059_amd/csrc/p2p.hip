@@ -101,7 +101,10 @@ __device__ inline void pair64(double rx, double ry, double rz, double r2, double
     c2 = fma(a1, f2, b * rz);
 }
 
-// FP32 versions (FP32 bulk mode): hardware reciprocal, rsqrt and exp2, degree-9 polynomial
+// FP32 versions (FP32 bulk mode): hardware reciprocal, rsqrt (+ one Newton step) and exp2,
+// degree-11 polynomial.  The exponent -xi^2 r^2 log2(e) reaches ~40, where one FP32 ulp is
+// ~4e-6, so it is formed and split into integer and fraction in FP64 (same VALU rate) and
+// only 2^fraction is taken in FP32.
 __device__ inline float screen_q32(float x)
 {
     const float d = x + (float)kScreenK;
@@ -114,13 +117,16 @@ __device__ inline float screen_q32(float x)
     return fmaf((float)kTwoOverSqrtPi, x, q);
 }
 
-__device__ inline void pair32(float rx, float ry, float rz, float r2, float f0, float f1, float f2,
-                              float xi, float xi2_log2e, float four_xi_over_sqrtpi, float& c0, float& c1,
+__device__ inline void pair32(float rx, float ry, float rz, float r2, double r2d, float f0, float f1, float f2,
+                              float xi, double xi2_log2e, float four_xi_over_sqrtpi, float& c0, float& c1,
                               float& c2)
 {
-    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float y = __builtin_amdgcn_rsqf(r2);
+    const float rinv = y * fmaf(-0.5f * r2 * y, y, 1.5f);
     const float x = xi * r2 * rinv;
-    const float e = __builtin_amdgcn_exp2f(-xi2_log2e * r2);
+    const double ea = -xi2_log2e * r2d;
+    const double en = rint(ea);
+    const float e = ldexpf(__builtin_amdgcn_exp2f((float)(ea - en)), (int)en);
     const float C = e * screen_q32(x);
     const float a1 = fmaf(C, rinv, -four_xi_over_sqrtpi * e);
     const float rf = rx * f0 + ry * f1 + rz * f2;
@@ -148,8 +154,8 @@ struct Pair<float> {
     __device__ static inline void eval(double rx, double ry, double rz, double r2, float f0, float f1,
                                        float f2, const PairArgs& a, float& c0, float& c1, float& c2)
     {
-        pair32((float)rx, (float)ry, (float)rz, (float)r2, f0, f1, f2, (float)a.xi,
-               (float)(a.xi2 * 1.4426950408889634), (float)a.four_xi_over_sqrtpi, c0, c1, c2);
+        pair32((float)rx, (float)ry, (float)rz, (float)r2, r2, f0, f1, f2, (float)a.xi,
+               a.xi2 * 1.4426950408889634, (float)a.four_xi_over_sqrtpi, c0, c1, c2);
     }
 };
 

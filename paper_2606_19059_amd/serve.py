@@ -86,6 +86,8 @@ class Server:
         self.plans: dict = {}
         self.plan_n_max = plan_n_max  # only bounds n; workspaces are sized per request
         self.clock0 = None
+        self.max_in_flight_bytes = 0  # statistics of the last run()
+        self.memory_waits = 0
 
     # -- plans and footprints -------------------------------------------------------------
 
@@ -129,6 +131,7 @@ class Server:
         job._keep = (x, f)  # inputs stay alive until the stream is done with them
         slot.job, slot.event = job, ev
         self.in_flight_bytes += job.footprint
+        self.max_in_flight_bytes = max(self.max_in_flight_bytes, self.in_flight_bytes)
 
     def _retire(self, slot):
         job = slot.job
@@ -148,6 +151,8 @@ class Server:
                 raise ValueError("request %d needs %d bytes, above the HBM budget %d" % (j.rid, j.footprint, self.budget))
         waiting = collections.deque(sorted(jobs, key=lambda j: j.arrival))
         done = []
+        self.max_in_flight_bytes = 0
+        self.memory_waits = 0
         self.clock0 = time.perf_counter()
         while waiting or any(s.job is not None for s in self.slots):
             for s in self.slots:
@@ -157,7 +162,10 @@ class Server:
             while waiting and waiting[0].arrival <= t:
                 job = waiting[0]
                 slot = next((s for s in self.slots if s.job is None), None)
-                if slot is None or self.in_flight_bytes + job.footprint > self.budget:
+                if slot is None:
+                    break
+                if self.in_flight_bytes + job.footprint > self.budget:
+                    self.memory_waits += 1
                     break
                 waiting.popleft()
                 self._admit(job, slot)

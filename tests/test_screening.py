@@ -42,4 +42,4 @@ def test_screening_polynomials_meet_their_bounds():
     e64 = np.max(np.abs(_eval(x, arrs["kScreenC64"], K, A, B) - ref))
     e32 = np.max(np.abs(_eval(x, arrs["kScreenC32"], K, A, B) - ref))
     assert e64 < 5e-15, e64
-    assert e32 < 2e-8, e32
+    assert e32 < 2e-9, e32
