@@ -55,7 +55,10 @@ typedef enum {
 enum {
     EWALD_FP64 = 0,      /* every step in FP64 */
     EWALD_FP32_BULK = 1, /* P2P, P2G, FFT, G2P in FP32; Fourier-space scaling, k = 0 and
-                            self terms, final sum in FP64 */
+                            self terms, final sum in FP64.  Below tol 1e-6 the grid and its
+                            transforms are kept in FP64 (the FP32 round trip through the
+                            3D FFT alone leaves ~2e-7 relative error); P2P and the window
+                            weights of G2P stay FP32 */
     EWALD_FLAG_P2P_FP64_ACC = 1 << 8, /* FP32 bulk: accumulate each particle's near-field
                                          sum in FP64 (automatic when tol < 1e-7) */
     EWALD_FLAG_STAGE_TIMERS = 1 << 9, /* record per-stage HIP events (see ewald_stage_ms) */
@@ -94,7 +97,7 @@ typedef struct {
     int32_t tile;             /* P2P cell edge, in grid cells */
     int32_t n_tiles[3];       /* P2P cells per dimension */
     int32_t stencil[3];       /* P2P neighbour half-width, in cells */
-    int32_t reserved;
+    int32_t fourier_fp64;     /* 1 when the grid, FFT, CNV and IFFT are FP64, 0 for FP32 */
     int64_t workspace_bytes;  /* ewald_workspace_bytes(plan, n_max) */
 } ewald_plan_info;
 

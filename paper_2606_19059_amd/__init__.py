@@ -76,7 +76,7 @@ class PlanInfo(ctypes.Structure):
         ("tile", ctypes.c_int32),
         ("n_tiles", ctypes.c_int32 * 3),
         ("stencil", ctypes.c_int32 * 3),
-        ("reserved", ctypes.c_int32),
+        ("fourier_fp64", ctypes.c_int32),
         ("workspace_bytes", ctypes.c_int64),
     ]
 
@@ -175,6 +175,7 @@ def _info_dict(info, precision):
         "h": tuple(info.h), "err_near": info.err_near, "err_far": info.err_far,
         "err_window": info.err_window, "tile": info.tile, "n_tiles": tuple(info.n_tiles),
         "stencil": tuple(info.stencil), "workspace_bytes": info.workspace_bytes,
+        "fourier_fp64": bool(info.fourier_fp64),
         "window": "kb" if q.precision & EWALD_FLAG_WINDOW_KB else "gaussian",
     }
 
@@ -266,7 +267,7 @@ class Plan:
 
         n = _check_particles(x, f)
         M = self.info["grid"]
-        dt = torch.float64 if self.precision == "fp64" else torch.float32
+        dt = torch.float64 if self.info["fourier_fp64"] else torch.float32
         g = torch.empty((3, M[0], M[1], M[2]), dtype=dt, device=x.device)
         wp, wb = self._ws_args(n, workspace, x.device)
         _check(fn(self._h, n, _ptr(x), _ptr(f), _ptr(g), wp, wb, _stream_handle(stream)))

@@ -182,6 +182,9 @@ double kb_hat(double k, double a, double beta)
     return 2.0 * a * hyp / std::cyl_bessel_i(0.0, beta);
 }
 
+// FP32 bulk: below this tolerance the grid and its transforms stay FP64
+constexpr double kFourierFp32MinTol = 1e-6;
+
 int64_t align256(int64_t v) { return (v + 255) & ~(int64_t)255; }
 
 }  // namespace
@@ -198,7 +201,7 @@ int64_t layout_work(const Plan& pl, int64_t n, char* base, Work* w)
         return p;
     };
     const int64_t nn = std::max<int64_t>(n, 1);
-    const size_t real = (pl.mode == EWALD_FP64) ? 8 : 4;
+    const size_t real = pl.grid64 ? 8 : 4;
     const size_t recsz = sizeof(Rec64);
     Work tmp;
     Work* o = w ? w : &tmp;
@@ -306,6 +309,7 @@ int validate_and_resolve(const ewald_params* in, Plan* pl)
 
     pl->p = p;
     pl->mode = mode;
+    pl->grid64 = mode == EWALD_FP64 || p.tol < kFourierFp32MinTol;
     pl->fp64acc = (p.precision & EWALD_FLAG_P2P_FP64_ACC) || p.tol < 1e-7;
     pl->timers = (p.precision & EWALD_FLAG_STAGE_TIMERS) != 0;
     pl->P = p.P;
@@ -347,6 +351,7 @@ int validate_and_resolve(const ewald_params* in, Plan* pl)
         info.h[d] = g.h[d];
         info.n_tiles[d] = g.NT[d];
         info.stencil[d] = g.S[d];
+    info.fourier_fp64 = pl->grid64 ? 1 : 0;
     }
     info.err_near = err_near(p.xi, p.r_c);
     info.err_far = err_far(p.xi, h);
@@ -499,7 +504,7 @@ int run(ewald_plan_t plan, int64_t n64, const double* x, const double* f, void* 
     const bool t = pl->timers && what != Out::Spread && what != Out::FarGrid;
     hipError_t e;
     auto mark = [&](int k) {
-        if (t) hipEventRecord(pl->ev[k], s);
+        if (t) (void)hipEventRecord(pl->ev[k], s);
     };
     mark(0);
     if ((e = launch_sort(*pl, w, n, x, f, s)) != hipSuccess) return hip_fail(e, "sort");
@@ -510,7 +515,7 @@ int run(ewald_plan_t plan, int64_t n64, const double* x, const double* f, void* 
     mark(2);
     if ((e = launch_p2g(*pl, w, n, s)) != hipSuccess) return hip_fail(e, "P2G");
     mark(3);
-    const size_t gbytes = (size_t)3 * pl->g.ncells * (pl->mode == EWALD_FP64 ? 8 : 4);
+    const size_t gbytes = (size_t)3 * pl->g.ncells * (pl->grid64 ? 8 : 4);
     if (what == Out::Spread) {
         e = hipMemcpyAsync(o1, w.grid, gbytes, hipMemcpyDeviceToDevice, s);
         return e == hipSuccess ? EWALD_OK : hip_fail(e, "grid copy");
@@ -585,9 +590,9 @@ int ewald_plan_destroy(ewald_plan_t plan)
 {
     if (!plan) return EWALD_OK;
     Plan* pl = reinterpret_cast<Plan*>(plan);
-    if (pl->d_tables) hipFree(pl->d_tables);
+    if (pl->d_tables) (void)hipFree(pl->d_tables);
     for (int k = 0; k <= kNumStages; ++k)
-        if (pl->ev[k]) hipEventDestroy(pl->ev[k]);
+        if (pl->ev[k]) (void)hipEventDestroy(pl->ev[k]);
     delete pl;
     return EWALD_OK;
 }

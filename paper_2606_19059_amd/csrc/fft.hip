@@ -335,7 +335,7 @@ hipError_t launch_fgc_t(const Plan& pl, const Work& w, hipStream_t s, bool inver
 
 hipError_t launch_fgc(const Plan& pl, const Work& w, hipStream_t s, bool inverse_too, bool cnv)
 {
-    if (pl.mode == EWALD_FP64) return launch_fgc_t<double>(pl, w, s, inverse_too, cnv);
+    if (pl.grid64) return launch_fgc_t<double>(pl, w, s, inverse_too, cnv);
     return launch_fgc_t<float>(pl, w, s, inverse_too, cnv);
 }
 

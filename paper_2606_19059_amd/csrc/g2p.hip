@@ -29,9 +29,9 @@ __device__ inline T wave_sum(T v)
 // partial sums are reduced with shuffles, and lane 0 writes the result.
 constexpr int kG2PPerWave = 16;
 
-template <typename T, int P>
+template <typename T, typename TG, int P>
 __global__ __launch_bounds__(64) void k_g2p(int n, const typename RecView<T>::Rec* __restrict__ rec,
-                                            const T* __restrict__ grid, Geometry g, WinArgs<T> wa,
+                                            const TG* __restrict__ grid, Geometry g, WinArgs<T> wa,
                                             double self_coef, const double* __restrict__ u_near,
                                             const double* __restrict__ f_in, double* __restrict__ u,
                                             double* __restrict__ u_near_out,
@@ -56,7 +56,7 @@ __global__ __launch_bounds__(64) void k_g2p(int n, const typename RecView<T>::Re
             sw[d][j] = window_weight_one<T, P>(j, td, wa);
         }
         __syncthreads();
-        T a0 = 0, a1 = 0, a2 = 0;
+        TG a0 = 0, a1 = 0, a2 = 0;
 #pragma unroll
         for (int pass = 0; pass < kPass; ++pass) {
             const int yz = pass * kWave + lane;
@@ -69,7 +69,7 @@ __global__ __launch_bounds__(64) void k_g2p(int n, const typename RecView<T>::Re
                 for (int ix = 0; ix < P; ++ix) {
                     const int gx = wrapi(c[0] - P / 2 + 1 + ix, M1);
                     const int64_t idx = (int64_t)gx * M2 * M3 + col;
-                    const T wv = sw[0][ix] * wyz;
+                    const TG wv = sw[0][ix] * wyz;
                     a0 += wv * grid[idx];
                     a1 += wv * grid[nc + idx];
                     a2 += wv * grid[2 * nc + idx];
@@ -98,29 +98,29 @@ __global__ __launch_bounds__(64) void k_g2p(int n, const typename RecView<T>::Re
 }
 
 
-template <typename T, int P>
+template <typename T, typename TG, int P>
 hipError_t launch_g2p_t(const Plan& pl, const Work& w, int n, const double* f, double* u, double* un,
                         double* uf, hipStream_t s)
 {
     const double self_coef = 4.0 * pl.xi / sqrt(M_PI);
-    hipLaunchKernelGGL((k_g2p<T, P>), dim3((n + kG2PPerWave - 1) / kG2PPerWave), dim3(kWave), 0, s, n,
-                       (const typename RecView<T>::Rec*)w.rec, (const T*)w.grid, pl.g, make_win_args<T>(pl),
+    hipLaunchKernelGGL((k_g2p<T, TG, P>), dim3((n + kG2PPerWave - 1) / kG2PPerWave), dim3(kWave), 0, s, n,
+                       (const typename RecView<T>::Rec*)w.rec, (const TG*)w.grid, pl.g, make_win_args<T>(pl),
                        self_coef, w.u_near, f, u, un, uf);
     return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, typename TG>
 hipError_t launch_g2p_p(const Plan& pl, const Work& w, int n, const double* f, double* u, double* un,
                         double* uf, hipStream_t s)
 {
     switch (pl.P) {
-    case 4: return launch_g2p_t<T, 4>(pl, w, n, f, u, un, uf, s);
-    case 6: return launch_g2p_t<T, 6>(pl, w, n, f, u, un, uf, s);
-    case 8: return launch_g2p_t<T, 8>(pl, w, n, f, u, un, uf, s);
-    case 10: return launch_g2p_t<T, 10>(pl, w, n, f, u, un, uf, s);
-    case 12: return launch_g2p_t<T, 12>(pl, w, n, f, u, un, uf, s);
-    case 14: return launch_g2p_t<T, 14>(pl, w, n, f, u, un, uf, s);
-    case 16: return launch_g2p_t<T, 16>(pl, w, n, f, u, un, uf, s);
+    case 4: return launch_g2p_t<T, TG, 4>(pl, w, n, f, u, un, uf, s);
+    case 6: return launch_g2p_t<T, TG, 6>(pl, w, n, f, u, un, uf, s);
+    case 8: return launch_g2p_t<T, TG, 8>(pl, w, n, f, u, un, uf, s);
+    case 10: return launch_g2p_t<T, TG, 10>(pl, w, n, f, u, un, uf, s);
+    case 12: return launch_g2p_t<T, TG, 12>(pl, w, n, f, u, un, uf, s);
+    case 14: return launch_g2p_t<T, TG, 14>(pl, w, n, f, u, un, uf, s);
+    case 16: return launch_g2p_t<T, TG, 16>(pl, w, n, f, u, un, uf, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -131,8 +131,9 @@ hipError_t launch_g2p(const Plan& pl, const Work& w, int n, const double* f, dou
                       double* u_near_out, double* u_far_out, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    if (pl.mode == EWALD_FP64) return launch_g2p_p<double>(pl, w, n, f, u, u_near_out, u_far_out, s);
-    return launch_g2p_p<float>(pl, w, n, f, u, u_near_out, u_far_out, s);
+    if (pl.mode == EWALD_FP64) return launch_g2p_p<double, double>(pl, w, n, f, u, u_near_out, u_far_out, s);
+    if (pl.grid64) return launch_g2p_p<float, double>(pl, w, n, f, u, u_near_out, u_far_out, s);
+    return launch_g2p_p<float, float>(pl, w, n, f, u, u_near_out, u_far_out, s);
 }
 
 }  // namespace ewald

@@ -53,6 +53,7 @@ struct Plan {
     double beta;           // Gaussian: 2 m^2 / P^2 (w0 = exp(-beta u^2), u = distance / h); KB: beta
     double xi, rc;
     int mode;              // EWALD_FP64 or EWALD_FP32_BULK
+    bool grid64;           // grid, FFT, CNV, IFFT in FP64 (always in FP64 mode)
     bool fp64acc;          // FP32 bulk: FP64 near-field accumulation
     bool timers;
     int device;

@@ -221,7 +221,7 @@ int p2g_max_runs() { return kMaxRuns; }
 hipError_t launch_p2g(const Plan& pl, const Work& w, int n, hipStream_t s)
 {
     (void)n;
-    if (pl.mode == EWALD_FP64) return launch_p2g_p<double>(pl, w, s);
+    if (pl.grid64) return launch_p2g_p<double>(pl, w, s);
     return launch_p2g_p<float>(pl, w, s);
 }
 

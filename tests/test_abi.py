@@ -90,3 +90,14 @@ def test_auto_grid_and_workspace():
 def test_explicit_parameters_are_kept():
     i = E.resolve((1, 1, 1), 1e-6, xi=9.0, r_c=0.3, grid=(32, 32, 32), P=10, window_shape=5.1)
     assert (i["xi"], i["r_c"], i["grid"], i["P"], i["window_shape"]) == (9.0, 0.3, (32, 32, 32), 10, 5.1)
+
+
+def test_fourier_stage_precision_follows_tolerance():
+    """FP32 bulk keeps the grid and its transforms in FP32 down to tol 1e-6, FP64 below."""
+    g = (64, 64, 64)
+    assert not E.resolve((1, 1, 1), 1e-6, grid=g, precision="fp32")["fourier_fp64"]
+    assert E.resolve((1, 1, 1), 1e-7, grid=g, precision="fp32")["fourier_fp64"]
+    assert E.resolve((1, 1, 1), 1e-4, grid=g, precision="fp64")["fourier_fp64"]
+    w32 = E.resolve((1, 1, 1), 1e-6, grid=g, precision="fp32", n_max=1000)["workspace_bytes"]
+    w64 = E.resolve((1, 1, 1), 1e-7, grid=g, precision="fp32", n_max=1000)["workspace_bytes"]
+    assert w64 - w32 >= 0.9 * 3 * 64 ** 3 * 4  # the FP64 grid (tile tables differ slightly)
