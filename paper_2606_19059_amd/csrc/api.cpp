@@ -325,9 +325,12 @@ int validate_and_resolve(const ewald_params* in, Plan* pl)
         g.M[d] = p.grid[d];
         g.h[d] = p.box[d] / p.grid[d];
     }
-    // P2P tile: edge ~ r_c / 2.5 grid cells, power of two in [2, 16], not above any M
-    int B = next_pow2(p.r_c / (2.5 * hmin) / std::sqrt(2.0));
-    B = std::max(2, std::min(16, B));
+    // P2P tile: the smallest power of two in [2, 16] whose tiles hold about 128 particles
+    // at n_max, so that the 64-target chunks of a tile are mostly full; not above any M
+    const double cells_per_volume = (double)p.grid[0] * p.grid[1] * p.grid[2] / (p.box[0] * p.box[1] * p.box[2]);
+    const double per_cell = (double)std::max<int64_t>(p.n_max, 1) / (cells_per_volume * p.box[0] * p.box[1] * p.box[2]);
+    int B = 2;
+    while (B < 16 && per_cell * B * B * B < 128.0) B *= 2;
     for (int d = 0; d < 3; ++d) B = std::min(B, g.M[d]);
     g.B = B;
     g.log2B = ilog2(B);

@@ -43,7 +43,7 @@ __global__ __launch_bounds__(64) void k_g2p(int n, const typename RecView<T>::Re
     const int M1 = g.M[0], M2 = g.M[1], M3 = g.M[2];
     const int64_t nc = g.ncells;
     const int64_t nn = n;
-    const int s0 = blockIdx.x * kG2PPerWave;
+    const int s0 = xcd_remap((int)blockIdx.x, (int)gridDim.x) * kG2PPerWave;
     const int s1 = min(s0 + kG2PPerWave, n);
     for (int s = s0; s < s1; ++s) {
         const auto& r = rec[s];

@@ -24,13 +24,33 @@ struct Geometry {
     int ntiles;       // NT1 NT2 NT3
 };
 
-// Sort key of grid cell (cx, cy, cz): tile-major, then lexicographic inside the tile,
-// so that each P2P tile is one contiguous range of sorted particles.
+// Interleave the bits of x (odd positions) and y (even positions), 4 bits each.
+__host__ __device__ inline int morton2(int x, int y)
+{
+    int k = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) k |= (((x >> i) & 1) << (2 * i + 1)) | (((y >> i) & 1) << (2 * i));
+    return k;
+}
+
+// Sort key of grid cell (cx, cy, cz): tile-major, so that each P2P tile is one contiguous
+// range of sorted particles; inside a tile the (x, y) columns follow a Morton curve (so a
+// run of consecutive particles, a P2P target chunk, fills a compact sub-block) and z is
+// fastest (so the cells of one column segment are consecutive keys, which P2G uses).
 __host__ __device__ inline int cell_key(int cx, int cy, int cz, const Geometry& g)
 {
     const int b = g.log2B, m = g.B - 1;
     const int tile = ((cx >> b) * g.NT[1] + (cy >> b)) * g.NT[2] + (cz >> b);
-    return (tile << (3 * b)) | (((((cx & m) << b) | (cy & m)) << b) | (cz & m));
+    return (tile << (3 * b)) | (morton2(cx & m, cy & m) << b) | (cz & m);
+}
+
+// Block index -> work item such that each XCD (blocks are dealt to the 8 XCDs round
+// robin) processes one contiguous range of items: neighbouring (cell-sorted) items then
+// share that XCD's L2.  A bijection on [0, nb).
+__device__ inline int xcd_remap(int b, int nb)
+{
+    const int x = b & 7, l = b >> 3, q = nb >> 3, r = nb & 7;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + l;
 }
 
 // Sorted particle record, FP64 mode: wrapped position (in [0, L)) and its grid cell, so

@@ -176,7 +176,7 @@ __global__ __launch_bounds__(64) void k_p2p(int n, const Rec64* __restrict__ rec
     __shared__ TF ringf[3][kRing];
     __shared__ unsigned short queue[kTest * kWave];
 
-    const int wave = uniform_i((int)blockIdx.x);
+    const int wave = uniform_i(xcd_remap((int)blockIdx.x, (int)gridDim.x));
     const int lane = threadIdx.x;
     const int total = chunk_off[g.ntiles];
     if (wave >= total) return;
@@ -329,14 +329,13 @@ hipError_t launch_p2p(const Plan& pl, const Work& w, int n, hipStream_t s)
     const int64_t waves = (int64_t)pl.g.ntiles + (n + kWave - 1) / kWave;
     const dim3 grid((unsigned)waves), block(kWave);
     const Rec64* rec = (const Rec64*)w.rec;
+    // FP32 bulk accumulates in FP64 as well: LDS atomic adds of FP64 are fast on gfx950,
+    // those of FP32 are not (measured: 3x slower kernel)
     if (pl.mode == EWALD_FP64)
         hipLaunchKernelGGL((k_p2p<double, double>), grid, block, 0, s, n, rec, w.start, w.chunk_off, pl.g, a,
                            w.u_near);
-    else if (pl.fp64acc)
-        hipLaunchKernelGGL((k_p2p<float, double>), grid, block, 0, s, n, rec, w.start, w.chunk_off, pl.g, a,
-                           w.u_near);
     else
-        hipLaunchKernelGGL((k_p2p<float, float>), grid, block, 0, s, n, rec, w.start, w.chunk_off, pl.g, a,
+        hipLaunchKernelGGL((k_p2p<float, double>), grid, block, 0, s, n, rec, w.start, w.chunk_off, pl.g, a,
                            w.u_near);
     return hipGetLastError();
 }
