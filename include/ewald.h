@@ -62,8 +62,13 @@ enum {
     EWALD_FLAG_P2P_FP64_ACC = 1 << 8, /* FP32 bulk: accumulate each particle's near-field
                                          sum in FP64 (automatic when tol < 1e-7) */
     EWALD_FLAG_STAGE_TIMERS = 1 << 9, /* record per-stage HIP events (see ewald_stage_ms) */
-    EWALD_FLAG_WINDOW_KB = 1 << 10    /* truncated Kaiser-Bessel window (Sec. 2.2) instead of the
+    EWALD_FLAG_WINDOW_KB = 1 << 10,   /* truncated Kaiser-Bessel window (Sec. 2.2) instead of the
                                          Gaussian: w0(d) = I0(beta sqrt(1 - (2d/(P h))^2)) / I0(beta) */
+    EWALD_FLAG_DETERMINISTIC = 1 << 11 /* bitwise reproducible results: P2P evaluates every pair
+                                          from both sides (about twice the pair work).  Without it
+                                          each pair is evaluated once and its two contributions
+                                          are added with atomics, so repeated evaluations agree to
+                                          rounding (~1e-16 relative), not bitwise */
 };
 
 /*

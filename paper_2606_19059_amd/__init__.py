@@ -25,6 +25,7 @@ EWALD_FP32_BULK = 1
 EWALD_FLAG_P2P_FP64_ACC = 1 << 8
 EWALD_FLAG_STAGE_TIMERS = 1 << 9
 EWALD_FLAG_WINDOW_KB = 1 << 10
+EWALD_FLAG_DETERMINISTIC = 1 << 11
 
 STAGES = ("sort", "p2p", "p2g", "fgc", "g2p", "total")
 
@@ -146,7 +147,7 @@ def _check_particles(x, f):
 
 
 def make_params(box, tol, xi=None, r_c=None, grid=None, P=None, precision="fp64", n_max=1 << 20,
-                window_shape=None, p2p_fp64_acc=False, timers=False, window="gaussian"):
+                window_shape=None, p2p_fp64_acc=False, timers=False, window="gaussian", deterministic=False):
     """The ewald_params struct for these arguments (None = derive from tol)."""
     p = Params()
     for d in range(3):
@@ -160,7 +161,8 @@ def make_params(box, tol, xi=None, r_c=None, grid=None, P=None, precision="fp64"
     if window not in ("gaussian", "kb"):
         raise ValueError("window must be 'gaussian' or 'kb'")
     p.precision = mode | (EWALD_FLAG_P2P_FP64_ACC if p2p_fp64_acc else 0) | (
-        EWALD_FLAG_STAGE_TIMERS if timers else 0) | (EWALD_FLAG_WINDOW_KB if window == "kb" else 0)
+        EWALD_FLAG_STAGE_TIMERS if timers else 0) | (EWALD_FLAG_WINDOW_KB if window == "kb" else 0) | (
+        EWALD_FLAG_DETERMINISTIC if deterministic else 0)
     p.reserved = 0
     p.n_max = int(n_max)
     p.window_shape = float(window_shape) if window_shape else 0.0
@@ -177,6 +179,7 @@ def _info_dict(info, precision):
         "stencil": tuple(info.stencil), "workspace_bytes": info.workspace_bytes,
         "fourier_fp64": bool(info.fourier_fp64),
         "window": "kb" if q.precision & EWALD_FLAG_WINDOW_KB else "gaussian",
+        "deterministic": bool(q.precision & EWALD_FLAG_DETERMINISTIC),
     }
 
 
@@ -197,10 +200,10 @@ class Plan:
     """
 
     def __init__(self, box, tol, xi=None, r_c=None, grid=None, P=None, precision="fp64", n_max=1 << 20,
-                 window_shape=None, p2p_fp64_acc=False, timers=False, window="gaussian"):
+                 window_shape=None, p2p_fp64_acc=False, timers=False, window="gaussian", deterministic=False):
         lib = load()
         p = make_params(box, tol, xi, r_c, grid, P, precision, n_max, window_shape, p2p_fp64_acc, timers,
-                        window)
+                        window, deterministic)
         h = ctypes.c_void_p()
         _check(lib.ewald_plan_create(ctypes.byref(p), ctypes.byref(h)))
         self._h = h

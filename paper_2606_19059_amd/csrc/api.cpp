@@ -236,7 +236,8 @@ int validate_and_resolve(const ewald_params* in, Plan* pl)
     const int mode = p.precision & 0xff;
     if (mode != EWALD_FP64 && mode != EWALD_FP32_BULK)
         return fail(EWALD_EINVAL, "unknown precision mode %d", mode);
-    if (p.precision & ~(0xff | EWALD_FLAG_P2P_FP64_ACC | EWALD_FLAG_STAGE_TIMERS | EWALD_FLAG_WINDOW_KB))
+    if (p.precision &
+        ~(0xff | EWALD_FLAG_P2P_FP64_ACC | EWALD_FLAG_STAGE_TIMERS | EWALD_FLAG_WINDOW_KB | EWALD_FLAG_DETERMINISTIC))
         return fail(EWALD_EINVAL, "unknown precision flags 0x%x", p.precision);
     if (mode == EWALD_FP32_BULK && p.tol < 1e-7)
         return fail(EWALD_EUNSUPPORTED, "tol = %g below 1e-7 needs the FP64 mode", p.tol);
@@ -310,7 +311,8 @@ int validate_and_resolve(const ewald_params* in, Plan* pl)
     pl->p = p;
     pl->mode = mode;
     pl->grid64 = mode == EWALD_FP64 || p.tol < kFourierFp32MinTol;
-    pl->fp64acc = (p.precision & EWALD_FLAG_P2P_FP64_ACC) || p.tol < 1e-7;
+    pl->fp64acc = true;  // FP64 near-field accumulation in both modes (EWALD_FLAG_P2P_FP64_ACC is implied)
+    pl->deterministic = (p.precision & EWALD_FLAG_DETERMINISTIC) != 0;
     pl->timers = (p.precision & EWALD_FLAG_STAGE_TIMERS) != 0;
     pl->P = p.P;
     pl->window_kb = kb;

@@ -4,7 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "../../include/ewald.h"
+#include "ewald.h"  // include/ (on the compiler include path)
 
 namespace ewald {
 
@@ -75,6 +75,7 @@ struct Plan {
     int mode;              // EWALD_FP64 or EWALD_FP32_BULK
     bool grid64;           // grid, FFT, CNV, IFFT in FP64 (always in FP64 mode)
     bool fp64acc;          // FP32 bulk: FP64 near-field accumulation
+    bool deterministic;    // bitwise reproducible P2P (one-sided pair evaluation)
     bool timers;
     int device;
     // device tables owned by the plan

@@ -33,6 +33,11 @@ namespace {
 struct PairArgs {
     double xi, xi2, rc2;
     double four_xi_over_sqrtpi;
+    double xi2_log2e;
+    // screening polynomial, passed by value so that the coefficients sit in scalar
+    // registers (an FMA then takes them as an operand, no per-pair register copies)
+    double c64[kScreenDeg64 + 1];
+    float c32[kScreenDeg32 + 1];
 };
 
 constexpr double kTwoOverSqrtPi = 1.1283791670955125739;
@@ -72,92 +77,83 @@ __device__ inline int lanes_below(unsigned long long m)
 }
 
 // erfcx(x) + 2x/sqrt(pi) for 0 <= x <= kScreenXmax (polynomial of screening.h)
-__device__ inline double screen_q64(double x)
+__device__ inline double screen_q64(double x, const PairArgs& a)
 {
     const double d = x + kScreenK;
     double r = __builtin_amdgcn_rcp(d);
     r = fma(fma(-d, r, 1.0), r, r);
     r = fma(fma(-d, r, 1.0), r, r);
     const double u = fma((x - kScreenK) * r, kScreenA, kScreenB);
-    double q = kScreenC64[kScreenDeg64];
+    double q = a.c64[kScreenDeg64];
 #pragma unroll
-    for (int k = kScreenDeg64 - 1; k >= 0; --k) q = fma(q, u, kScreenC64[k]);
+    for (int k = kScreenDeg64 - 1; k >= 0; --k) q = fma(q, u, a.c64[k]);
     return fma(kTwoOverSqrtPi, x, q);
 }
 
-// G^N(r) f for 0 < r^2 < r_c^2
-__device__ inline void pair64(double rx, double ry, double rz, double r2, double f0, double f1, double f2,
-                              const PairArgs& a, double& c0, double& c1, double& c2)
+// Coefficients of G^N(r) f = a1 f + b (r.f) r for 0 < r^2 < r_c^2 (FP64)
+__device__ inline void coef64(double r2, const PairArgs& a, double& a1, double& b)
 {
     const double rinv = rsqrt(r2);
     const double x = a.xi * r2 * rinv;
     const double e = exp(-a.xi2 * r2);
-    const double C = e * screen_q64(x);
-    const double a1 = fma(C, rinv, -a.four_xi_over_sqrtpi * e);
-    const double rf = rx * f0 + ry * f1 + rz * f2;
-    const double b = C * rinv * (rinv * rinv) * rf;
-    c0 = fma(a1, f0, b * rx);
-    c1 = fma(a1, f1, b * ry);
-    c2 = fma(a1, f2, b * rz);
+    const double C = e * screen_q64(x, a);
+    a1 = fma(C, rinv, -a.four_xi_over_sqrtpi * e);
+    b = C * rinv * (rinv * rinv);
 }
 
 // FP32 versions (FP32 bulk mode): hardware reciprocal, rsqrt (+ one Newton step) and exp2,
 // degree-11 polynomial.  The exponent -xi^2 r^2 log2(e) reaches ~40, where one FP32 ulp is
 // ~4e-6, so it is formed and split into integer and fraction in FP64 (same VALU rate) and
 // only 2^fraction is taken in FP32.
-__device__ inline float screen_q32(float x)
+__device__ inline float screen_q32(float x, const PairArgs& a)
 {
     const float d = x + (float)kScreenK;
     float r = __builtin_amdgcn_rcpf(d);
     r = fmaf(fmaf(-d, r, 1.0f), r, r);
     const float u = fmaf((x - (float)kScreenK) * r, (float)kScreenA, (float)kScreenB);
-    float q = (float)kScreenC32[kScreenDeg32];
+    float q = a.c32[kScreenDeg32];
 #pragma unroll
-    for (int k = kScreenDeg32 - 1; k >= 0; --k) q = fmaf(q, u, (float)kScreenC32[k]);
+    for (int k = kScreenDeg32 - 1; k >= 0; --k) q = fmaf(q, u, a.c32[k]);
     return fmaf((float)kTwoOverSqrtPi, x, q);
 }
 
-__device__ inline void pair32(float rx, float ry, float rz, float r2, double r2d, float f0, float f1, float f2,
-                              float xi, double xi2_log2e, float four_xi_over_sqrtpi, float& c0, float& c1,
-                              float& c2)
+__device__ inline void coef32(double r2d, const PairArgs& a, float& a1, float& b)
 {
+    const float r2 = (float)r2d;
     const float y = __builtin_amdgcn_rsqf(r2);
     const float rinv = y * fmaf(-0.5f * r2 * y, y, 1.5f);
-    const float x = xi * r2 * rinv;
-    const double ea = -xi2_log2e * r2d;
+    const float x = (float)a.xi * r2 * rinv;
+    const double ea = -a.xi2_log2e * r2d;
     const double en = rint(ea);
     const float e = ldexpf(__builtin_amdgcn_exp2f((float)(ea - en)), (int)en);
-    const float C = e * screen_q32(x);
-    const float a1 = fmaf(C, rinv, -four_xi_over_sqrtpi * e);
-    const float rf = rx * f0 + ry * f1 + rz * f2;
-    const float b = C * rinv * (rinv * rinv) * rf;
-    c0 = fmaf(a1, f0, b * rx);
-    c1 = fmaf(a1, f1, b * ry);
-    c2 = fmaf(a1, f2, b * rz);
+    const float C = e * screen_q32(x, a);
+    a1 = fmaf(C, rinv, -(float)a.four_xi_over_sqrtpi * e);
+    b = C * rinv * (rinv * rinv);
 }
 
-// Pair evaluation in the formula precision TF (double: FP64 path; float: FP32 bulk).
+// Pair coefficients in the formula precision TF (double: FP64 path; float: FP32 bulk).
 template <typename TF>
-struct Pair;
-
+__device__ inline void coef(double r2, const PairArgs& a, TF& a1, TF& b);
 template <>
-struct Pair<double> {
-    __device__ static inline void eval(double rx, double ry, double rz, double r2, double f0, double f1,
-                                       double f2, const PairArgs& a, double& c0, double& c1, double& c2)
-    {
-        pair64(rx, ry, rz, r2, f0, f1, f2, a, c0, c1, c2);
-    }
-};
-
+__device__ inline void coef<double>(double r2, const PairArgs& a, double& a1, double& b)
+{
+    coef64(r2, a, a1, b);
+}
 template <>
-struct Pair<float> {
-    __device__ static inline void eval(double rx, double ry, double rz, double r2, float f0, float f1,
-                                       float f2, const PairArgs& a, float& c0, float& c1, float& c2)
-    {
-        pair32((float)rx, (float)ry, (float)rz, (float)r2, r2, f0, f1, f2, (float)a.xi,
-               a.xi2 * 1.4426950408889634, (float)a.four_xi_over_sqrtpi, c0, c1, c2);
-    }
-};
+__device__ inline void coef<float>(double r2, const PairArgs& a, float& a1, float& b)
+{
+    coef32(r2, a, a1, b);
+}
+
+// c = a1 f + b (r.f) r
+template <typename TF>
+__device__ inline void apply(TF a1, TF b, TF rx, TF ry, TF rz, TF f0, TF f1, TF f2, TF& c0, TF& c1, TF& c2)
+{
+    const TF rf = (rx * f0 + ry * f1 + rz * f2) * b;
+    c0 = a1 * f0 + rf * rx;
+    c1 = a1 * f1 + rf * ry;
+    c2 = a1 * f2 + rf * rz;
+}
 
 constexpr int kRing = 128;   // LDS ring of filtered candidate sources
 constexpr int kTest = 32;    // sources tested per round (queue <= kTest * 64 pairs)
@@ -233,8 +229,9 @@ __global__ __launch_bounds__(64) void k_p2p(int n, const Rec64* __restrict__ rec
                 const double ry = tgt[1][tt] - ring[1][slot];
                 const double rz = tgt[2][tt] - ring[2][slot];
                 const double r2 = rx * rx + ry * ry + rz * rz;
-                TF c0, c1, c2;
-                Pair<TF>::eval(rx, ry, rz, r2, ringf[0][slot], ringf[1][slot], ringf[2][slot], a, c0, c1, c2);
+                TF a1, b, c0, c1, c2;
+                coef<TF>(r2, a, a1, b);
+                apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, ringf[0][slot], ringf[1][slot], ringf[2][slot], c0, c1, c2);
                 atomicAdd(&acc[0][tt], (TA)c0);
                 atomicAdd(&acc[1][tt], (TA)c1);
                 atomicAdd(&acc[2][tt], (TA)c2);
@@ -316,6 +313,218 @@ __global__ __launch_bounds__(64) void k_p2p(int n, const Rec64* __restrict__ rec
     }
 }
 
+// ---------------------------------------------------------------- symmetric form
+// G^N is even in r, so one evaluation of a pair (i, j) gives both G^N(r) f_j (to u_i) and
+// G^N(r) f_i (to u_j).  Every unordered pair is visited once: a wave walks only the upper
+// half of the neighbour-tile offsets D (lexicographically D > 0), plus its own tile (D = 0)
+// restricted to sources with a larger sorted index than the target; the mirrored offset
+// -D carries the same pairs.  The target side accumulates in LDS as before; the source
+// side accumulates per ring slot in LDS and is added to u^N with one FP64 atomic per
+// component and source when the slot retires.  u^N is zeroed first.  The order of those
+// atomic additions varies between runs, so results agree to rounding, not bitwise
+// (the one-sided kernel above is the reproducible variant).
+//
+// Candidates are tested in diagonal order (lane t tests ring source (t + j) mod 32 at
+// step j), so that the queued pairs of one drain round have distinct targets and at most
+// two lanes per source: few conflicts in the LDS atomics of either side.
+constexpr int kSymRing = 64;
+constexpr int kSymTest = 32;
+constexpr int kFar = 1 << 30;  // ring key offset of sources outside the targets' own tile
+
+__global__ void k_zero_f64(double* __restrict__ p, int64_t count)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0.0;
+}
+
+template <typename TF>
+__global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__ rec,
+                                                const int* __restrict__ start,
+                                                const int* __restrict__ chunk_off, Geometry g,
+                                                PairArgs a, double* __restrict__ u_near)
+{
+    __shared__ double tgt[3][kWave];
+    __shared__ TF tgtf[3][kWave];
+    __shared__ double acc[3][kWave];
+    __shared__ double ring[3][kSymRing];
+    __shared__ TF ringf[3][kSymRing];
+    __shared__ int ringk[kSymRing];
+    __shared__ double racc[3][kSymRing];
+    __shared__ unsigned short queue[kSymTest * kWave];
+    static_assert(kSymRing == kWave, "one ring slot per lane");
+
+    const int wave = uniform_i(xcd_remap((int)blockIdx.x, (int)gridDim.x));
+    const int lane = threadIdx.x;
+    const int total = chunk_off[g.ntiles];
+    if (wave >= total) return;
+
+    int lo = 0, hi = g.ntiles;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (chunk_off[mid] <= wave) lo = mid; else hi = mid;
+    }
+    const int t = lo;
+    const int per = 1 << (3 * g.log2B);
+    const int t_end = start[(t + 1) * per];
+    const int first = start[t * per] + (wave - chunk_off[t]) * kWave;
+    const int i = first + lane;
+    const bool active = i < t_end;
+    const Rec64 me = rec[active ? i : first];
+
+    const int tc[3] = {t / (g.NT[1] * g.NT[2]), (t / g.NT[2]) % g.NT[1], t % g.NT[2]};
+    double w[3], blo[3], bhi[3], tx[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        w[d] = g.B * g.h[d];
+        blo[d] = uniform_d(wave_min(me.x[d]));
+        bhi[d] = uniform_d(wave_max(me.x[d]));
+        tx[d] = active ? me.x[d] : 1e30;  // an inactive lane accepts no pair
+        tgt[d][lane] = tx[d];
+        tgtf[d][lane] = (TF)me.f[d];
+        acc[d][lane] = 0.0;
+        racc[d][lane] = 0.0;
+    }
+    __syncthreads();
+
+    int rhead = 0, rcount = 0;
+
+    auto process = [&](int cnt) {
+        int qn = 0;
+        const int l0 = lane % cnt;
+        for (int j = 0; j < cnt; ++j) {
+            int sl = l0 + j;
+            if (sl >= cnt) sl -= cnt;
+            const int slot = (rhead + sl) & (kSymRing - 1);
+            const double rx = tx[0] - ring[0][slot], ry = tx[1] - ring[1][slot], rz = tx[2] - ring[2][slot];
+            const double r2 = rx * rx + ry * ry + rz * rz;
+            const bool pass = (r2 < a.rc2) && (r2 > 0.0) && (ringk[slot] > i);
+            const unsigned long long b = __ballot(pass);
+            if (pass) queue[qn + lanes_below(b)] = (unsigned short)(lane | (sl << 6));
+            qn += __popcll(b);
+        }
+        __syncthreads();
+        for (int q0 = 0; q0 < qn; q0 += kWave) {
+            const int k = q0 + lane;
+            if (k < qn) {
+                const int e = queue[k];
+                const int tt = e & (kWave - 1);
+                const int slot = (rhead + (e >> 6)) & (kSymRing - 1);
+                const double rx = tgt[0][tt] - ring[0][slot];
+                const double ry = tgt[1][tt] - ring[1][slot];
+                const double rz = tgt[2][tt] - ring[2][slot];
+                const double r2 = rx * rx + ry * ry + rz * rz;
+                TF a1, b, c0, c1, c2, d0, d1, d2;
+                coef<TF>(r2, a, a1, b);
+                apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, ringf[0][slot], ringf[1][slot], ringf[2][slot], c0, c1, c2);
+                apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, tgtf[0][tt], tgtf[1][tt], tgtf[2][tt], d0, d1, d2);
+                atomicAdd(&acc[0][tt], (double)c0);
+                atomicAdd(&acc[1][tt], (double)c1);
+                atomicAdd(&acc[2][tt], (double)c2);
+                atomicAdd(&racc[0][slot], (double)d0);
+                atomicAdd(&racc[1][slot], (double)d1);
+                atomicAdd(&racc[2][slot], (double)d2);
+            }
+        }
+        __syncthreads();
+        // retire the cnt ring sources: their source-side sums go to u^N
+        if (lane < cnt) {
+            const int slot = (rhead + lane) & (kSymRing - 1);
+            const double v0 = racc[0][slot], v1 = racc[1][slot], v2 = racc[2][slot];
+            if (v0 != 0.0 || v1 != 0.0 || v2 != 0.0) {
+                const int64_t jj = ringk[slot] & (kFar - 1);
+                unsafeAtomicAdd(&u_near[jj], v0);
+                unsafeAtomicAdd(&u_near[(int64_t)n + jj], v1);
+                unsafeAtomicAdd(&u_near[2 * (int64_t)n + jj], v2);
+                racc[0][slot] = 0.0;
+                racc[1][slot] = 0.0;
+                racc[2][slot] = 0.0;
+            }
+        }
+        __syncthreads();
+    };
+
+    for (int dx = 0; dx <= g.S[0]; ++dx) {
+        const int ux = tc[0] + dx;
+        const int fx = floor_div(ux, g.NT[0]);
+        const int wx = ux - fx * g.NT[0];
+        const double shx = fx * g.L[0];
+        const double gx = fmax(0.0, fmax(ux * w[0] - bhi[0], blo[0] - (ux + 1) * w[0]));
+        for (int dy = (dx == 0 ? 0 : -g.S[1]); dy <= g.S[1]; ++dy) {
+            const int uy = tc[1] + dy;
+            const int fy = floor_div(uy, g.NT[1]);
+            const int wy = uy - fy * g.NT[1];
+            const double shy = fy * g.L[1];
+            const double gy = fmax(0.0, fmax(uy * w[1] - bhi[1], blo[1] - (uy + 1) * w[1]));
+            if (gx * gx + gy * gy >= a.rc2) continue;
+            for (int dz = (dx == 0 && dy == 0 ? 0 : -g.S[2]); dz <= g.S[2]; ++dz) {
+                const int uz = tc[2] + dz;
+                const int fz = floor_div(uz, g.NT[2]);
+                const int wz = uz - fz * g.NT[2];
+                const double shz = fz * g.L[2];
+                const double gz = fmax(0.0, fmax(uz * w[2] - bhi[2], blo[2] - (uz + 1) * w[2]));
+                if (gx * gx + gy * gy + gz * gz >= a.rc2) continue;
+                const bool own = (dx == 0 && dy == 0 && dz == 0);
+                const int nt = (wx * g.NT[1] + wy) * g.NT[2] + wz;
+                // own tile: sources below the first target can pair with none of them
+                const int sa = own ? first : start[nt * per], sb = start[(nt + 1) * per];
+                const int koff = own ? 0 : kFar;
+                for (int base = sa; base < sb; base += kWave) {
+                    const int s = base + lane;
+                    bool keep = false;
+                    double sx = 0, sy = 0, sz = 0, f0 = 0, f1 = 0, f2 = 0;
+                    if (s < sb) {
+                        const Rec64& q = rec[s];
+                        sx = q.x[0] + shx;
+                        sy = q.x[1] + shy;
+                        sz = q.x[2] + shz;
+                        f0 = q.f[0];
+                        f1 = q.f[1];
+                        f2 = q.f[2];
+                        const double ex = fmax(0.0, fmax(blo[0] - sx, sx - bhi[0]));
+                        const double ey = fmax(0.0, fmax(blo[1] - sy, sy - bhi[1]));
+                        const double ez = fmax(0.0, fmax(blo[2] - sz, sz - bhi[2]));
+                        keep = ex * ex + ey * ey + ez * ez < a.rc2;
+                    }
+                    // append in two halves so the 64-slot ring never holds more than 63
+#pragma unroll
+                    for (int half = 0; half < 2; ++half) {
+                        const bool mine = keep && ((lane >> 5) == half);
+                        const unsigned long long bm = __ballot(mine);
+                        if (mine) {
+                            const int slot = (rhead + rcount + lanes_below(bm)) & (kSymRing - 1);
+                            ring[0][slot] = sx;
+                            ring[1][slot] = sy;
+                            ring[2][slot] = sz;
+                            ringf[0][slot] = (TF)f0;
+                            ringf[1][slot] = (TF)f1;
+                            ringf[2][slot] = (TF)f2;
+                            ringk[slot] = koff + s;
+                        }
+                        rcount += __popcll(bm);
+                        __syncthreads();
+                        if (rcount >= kSymTest) {
+                            process(kSymTest);
+                            rhead = (rhead + kSymTest) & (kSymRing - 1);
+                            rcount -= kSymTest;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    while (rcount > 0) {
+        const int c = rcount < kSymTest ? rcount : kSymTest;
+        process(c);
+        rhead = (rhead + c) & (kSymRing - 1);
+        rcount -= c;
+    }
+    if (active) {
+        unsafeAtomicAdd(&u_near[i], acc[0][lane]);
+        unsafeAtomicAdd(&u_near[(int64_t)n + i], acc[1][lane]);
+        unsafeAtomicAdd(&u_near[2 * (int64_t)n + i], acc[2][lane]);
+    }
+}
+
 }  // namespace
 
 hipError_t launch_p2p(const Plan& pl, const Work& w, int n, hipStream_t s)
@@ -326,16 +535,31 @@ hipError_t launch_p2p(const Plan& pl, const Work& w, int n, hipStream_t s)
     a.xi2 = pl.xi * pl.xi;
     a.rc2 = pl.rc * pl.rc;
     a.four_xi_over_sqrtpi = 4.0 * pl.xi / sqrt(M_PI);
+    a.xi2_log2e = a.xi2 * 1.4426950408889634;
+    for (int k = 0; k <= kScreenDeg64; ++k) a.c64[k] = kScreenC64[k];
+    for (int k = 0; k <= kScreenDeg32; ++k) a.c32[k] = (float)kScreenC32[k];
     const int64_t waves = (int64_t)pl.g.ntiles + (n + kWave - 1) / kWave;
     const dim3 grid((unsigned)waves), block(kWave);
     const Rec64* rec = (const Rec64*)w.rec;
-    // FP32 bulk accumulates in FP64 as well: LDS atomic adds of FP64 are fast on gfx950,
-    // those of FP32 are not (measured: 3x slower kernel)
-    if (pl.mode == EWALD_FP64)
-        hipLaunchKernelGGL((k_p2p<double, double>), grid, block, 0, s, n, rec, w.start, w.chunk_off, pl.g, a,
+    const bool f64 = pl.mode == EWALD_FP64;
+    if (pl.deterministic) {
+        // FP32 bulk accumulates in FP64 as well: LDS atomic adds of FP64 are fast on
+        // gfx950, those of FP32 are not (measured: 3x slower kernel)
+        if (f64)
+            hipLaunchKernelGGL((k_p2p<double, double>), grid, block, 0, s, n, rec, w.start, w.chunk_off, pl.g,
+                               a, w.u_near);
+        else
+            hipLaunchKernelGGL((k_p2p<float, double>), grid, block, 0, s, n, rec, w.start, w.chunk_off, pl.g,
+                               a, w.u_near);
+        return hipGetLastError();
+    }
+    const int64_t cnt = 3 * (int64_t)n;
+    hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, w.u_near, cnt);
+    if (f64)
+        hipLaunchKernelGGL((k_p2p_sym<double>), grid, block, 0, s, n, rec, w.start, w.chunk_off, pl.g, a,
                            w.u_near);
     else
-        hipLaunchKernelGGL((k_p2p<float, double>), grid, block, 0, s, n, rec, w.start, w.chunk_off, pl.g, a,
+        hipLaunchKernelGGL((k_p2p_sym<float>), grid, block, 0, s, n, rec, w.start, w.chunk_off, pl.g, a,
                            w.u_near);
     return hipGetLastError();
 }

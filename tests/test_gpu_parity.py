@@ -49,9 +49,9 @@ CASES = {
 }
 
 
-def make_plan(E, name, n_max):
+def make_plan(E, name, n_max, **kw):
     box, grid, xi, rc, P, m = CASES[name]
-    return E.Plan(box, 1e-6, xi=xi, r_c=rc, grid=grid, P=P, window_shape=m, n_max=n_max)
+    return E.Plan(box, 1e-6, xi=xi, r_c=rc, grid=grid, P=P, window_shape=m, n_max=n_max, **kw)
 
 
 def test_tiny_eval_runs():
@@ -197,12 +197,16 @@ def test_all_particles_in_one_cell():
 
 
 def test_deterministic_and_permutation_equivariant():
+    """With EWALD_FLAG_DETERMINISTIC repeated evaluations agree bitwise; the default
+    (symmetric P2P with atomics) agrees with it to rounding."""
     E = _E()
-    pl = make_plan(E, "aniso_P12", 3000)
+    pl = make_plan(E, "aniso_P12", 3000, deterministic=True)
     x, f = W.particles(3000, CASES["aniso_P12"][0], seed=12)
     a = host(pl.eval(dev(x), dev(f)))
     b = host(pl.eval(dev(x), dev(f)))
     assert np.array_equal(a, b)
+    s = host(make_plan(E, "aniso_P12", 3000).eval(dev(x), dev(f)))
+    assert np.max(np.abs(s - a)) < 1e-13 * np.max(np.abs(a))
     p = np.random.default_rng(0).permutation(3000)
     c = host(pl.eval(dev(x[:, p]), dev(f[:, p])))
     assert np.max(np.abs(c - a[:, p])) < 1e-12 * np.max(np.abs(a))
