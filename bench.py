@@ -26,9 +26,13 @@ METRIC = "particles/s full Stokeslet Ewald eval at 1e-6 rel err; P2G GB/s; p50/p
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 FP32_VECTOR_TFLOPS = 157.3
-# algorithmic cost of one P2P pair inside r_c (documented in the design notes): 39
-# add/mul (FMA = 2) of the G^N f formula + 7 per special function (rsqrt, exp, erfc)
+# algorithmic cost of one (target, source) pair inside r_c (documented in the design notes):
+# 39 add/mul (FMA = 2) of the G^N f formula + 7 per special function (rsqrt, exp, erfc).
+# Counted per ordered pair, whatever the kernel executes (the symmetric kernel evaluates the
+# shared coefficients once per unordered pair).
 P2P_FLOPS_PER_PAIR = 60.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c2_fp64_p2p_traffic.json")
+P2P_SOURCES = ("p2p.hip", "internal.h", "screening.h")
 
 
 def log(*a):
@@ -72,6 +76,47 @@ def stage_roofline(stages, n, ncell, P, real, pairs, alu_peak_tflops):
     return out
 
 
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in P2P_SOURCES:
+        with open(os.path.join(ROOT, "paper_2606_19059_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE runs, scaled by a plain copy's readings), or None when the summary is absent,
+    names another kernel, or was taken from different kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel") != kernel or t.get("source_sha256") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def timed_evals(plan, x, f, steps, warmup):
+    """Median device ms of `steps` evaluations (stage timers of the plan)."""
+    import torch
+
+    ws = plan.workspace(x.shape[1], x.device)
+    u = torch.empty_like(x)
+    for _ in range(warmup):
+        plan.eval(x, f, out=u, workspace=ws)
+    torch.cuda.synchronize()
+    tot = []
+    for _ in range(steps):
+        plan.eval(x, f, out=u, workspace=ws)
+        torch.cuda.synchronize()
+        tot.append(plan.stage_ms()["total"])
+    return float(np.median(tot)), u
+
+
 def serving_leg(n_requests):
     """Stream of independent suspensions (N log-uniform in [1e3, 1e6], cubic or 1x1x2 box,
     uniform or blobs, tol in {1e-4, 1e-6, 1e-8}): saturated throughput with every request
@@ -113,8 +158,11 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--P", type=int, default=0, help="window support (0: derive from tol)")
     ap.add_argument("--precision", default=None)
-    ap.add_argument("--cpu-sample", type=int, default=24, help="oracle targets for accuracy + CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="host time budget of the oracle sample (accuracy + CPU baseline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra-plans", action="store_true",
+                    help="skip the cost-model plan and Kaiser-Bessel legs")
     ap.add_argument("--serve-requests", type=int, default=40,
                     help="requests in the serving leg (Poisson stream of independent suspensions; 0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -181,11 +229,16 @@ def main():
     # accuracy on sampled targets against the classical FP64 oracle (also the CPU baseline)
     rel_err = None
     cpu = None
-    if args.cpu_sample > 0 and not args.no_cpu_baseline:
+    if args.cpu_seconds > 0 and not args.no_cpu_baseline:
         import oracle
 
-        tgt = W.sample_targets(wl.n, args.cpu_sample, seed=100 + 2)
+        # a 16-target probe sizes the timed sample to about --cpu-seconds of host work
         u_np = u.cpu().numpy()
+        tc = time.perf_counter()
+        oracle.ewald_sum(x_np, f_np, wl.box, targets=W.sample_targets(wl.n, 16, seed=100 + 2))
+        probe_s = time.perf_counter() - tc
+        n_tgt = int(max(16, min(4096, 16 * args.cpu_seconds / max(probe_s, 1e-3))))
+        tgt = W.sample_targets(wl.n, n_tgt, seed=100 + 2)
         tc = time.perf_counter()
         ref = oracle.ewald_sum(x_np, f_np, wl.box, targets=tgt)
         cpu_s = time.perf_counter() - tc
@@ -205,17 +258,36 @@ def main():
     p2p_s = stages["p2p"] * 1e-3
     peak = FP64_VECTOR_TFLOPS if precision == "fp64" else FP32_VECTOR_TFLOPS
     achieved = (pairs * P2P_FLOPS_PER_PAIR / p2p_s / 1e12) if pairs else None
+    kernel = "k_p2p_sym<double>" if precision == "fp64" else "k_p2p_sym<float>"
     roofline = {
-        "kernel": "k_p2p<double, double>" if precision == "fp64" else "k_p2p<float, %s>" % (
-            "double" if (info["mode_flags"] & E.EWALD_FLAG_P2P_FP64_ACC or wl.tol < 1e-7) else "float"),
+        "kernel": kernel,
         "bound": "alu",
         "achieved": achieved,
         "peak": peak,
         "unit": "TFLOP/s",
         "frac": (achieved / peak) if achieved else None,
-        "traffic": None,
-        "per_unit": "%g flop per pair inside r_c; %.4g pairs per launch" % (P2P_FLOPS_PER_PAIR, pairs or 0),
+        "traffic": measured_traffic(kernel) if (wl.name == "c2" and precision == "fp64") else None,
+        "per_unit": "%g flop per (target, source) pair inside r_c; %.4g ordered pairs per launch"
+                    % (P2P_FLOPS_PER_PAIR, pairs or 0),
     }
+    # the same N and tolerance with the plan the cost model picks from the tolerance alone,
+    # and with the Kaiser-Bessel window on the configured grid
+    legs = {}
+    if not args.no_extra_plans:
+        auto = E.Plan(wl.box, wl.tol, precision=precision, n_max=wl.n, timers=True)
+        ms_auto, _ = timed_evals(auto, x, f, 5, 2)
+        legs["model_plan"] = {"grid": list(auto.info["grid"]), "P": auto.info["P"], "r_c": auto.info["r_c"],
+                              "predicted_ms": auto.info["predicted_ms"], "measured_ms": ms_auto,
+                              "particles_per_s": wl.n / (ms_auto * 1e-3)}
+        del auto
+        kbp = E.Plan(wl.box, wl.tol, grid=wl.grid, precision=precision, n_max=wl.n, timers=True, window="kb")
+        ms_kb, u_kb = timed_evals(kbp, x, f, 5, 2)
+        legs["kb_window"] = {"grid": list(kbp.info["grid"]), "P": kbp.info["P"], "measured_ms": ms_kb,
+                             "particles_per_s": wl.n / (ms_kb * 1e-3),
+                             "rel_err_vs_gaussian_window_result": float(
+                                 (torch.linalg.norm(u_kb - u) / torch.linalg.norm(u)).item())}
+        del kbp, u_kb
+        log("extra plans:", json.dumps(legs))
     # P2G GB/s: algorithmic bytes = particle reads (6 reals) + one write of the 3-component grid
     real = 8 if precision == "fp64" else 4
     ncell = info["grid"][0] * info["grid"][1] * info["grid"][2]
@@ -252,6 +324,7 @@ def main():
             "p2g_GBs": p2g_gbs, "p50_ms": p50, "p99_ms": p99, "stage_roofline": per_stage,
         },
         "serving": serving,
+        "other_plans": legs,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -75,8 +75,11 @@ enum {
  * Plan parameters.  Any parameter given as <= 0 is derived from `tol`
  * following the error split of Sec. 2.3 (eq. (ese), each error term held to
  * tol/3): xi from the grid spacing (E^F), r_c from xi (E^N), the window
- * support P and shape from the Gaussian-window error model, the grid from
- * r_c when neither grid nor xi is given.
+ * support P and shape from the window's error model.  When grid, xi and r_c
+ * are all left to derive, every power-of-two grid is resolved this way and the
+ * one with the smallest predicted device time for n_max particles is taken
+ * (the plan cost model, Sec. 2.3's parameter choice made by measured cost);
+ * when xi or r_c is given, the grid is the coarsest that resolves xi.
  */
 typedef struct {
     double box[3];       /* L1, L2, L3 > 0: orthorhombic, triply periodic */
@@ -104,6 +107,8 @@ typedef struct {
     int32_t stencil[3];       /* P2P neighbour half-width, in cells */
     int32_t fourier_fp64;     /* 1 when the grid, FFT, CNV and IFFT are FP64, 0 for FP32 */
     int64_t workspace_bytes;  /* ewald_workspace_bytes(plan, n_max) */
+    double predicted_ms;      /* device time of one evaluation of n_max particles predicted by
+                                 the plan cost model (uniform particles; MI355X-calibrated) */
 } ewald_plan_info;
 
 /* Create a plan (host call; allocates the plan's small device tables on the

@@ -79,6 +79,7 @@ class PlanInfo(ctypes.Structure):
         ("stencil", ctypes.c_int32 * 3),
         ("fourier_fp64", ctypes.c_int32),
         ("workspace_bytes", ctypes.c_int64),
+        ("predicted_ms", ctypes.c_double),
     ]
 
 
@@ -178,6 +179,7 @@ def _info_dict(info, precision):
         "err_window": info.err_window, "tile": info.tile, "n_tiles": tuple(info.n_tiles),
         "stencil": tuple(info.stencil), "workspace_bytes": info.workspace_bytes,
         "fourier_fp64": bool(info.fourier_fp64),
+        "predicted_ms": info.predicted_ms,
         "window": "kb" if q.precision & EWALD_FLAG_WINDOW_KB else "gaussian",
         "deterministic": bool(q.precision & EWALD_FLAG_DETERMINISTIC),
     }

@@ -185,6 +185,80 @@ double kb_hat(double k, double a, double beta)
 // FP32 bulk: below this tolerance the grid and its transforms stay FP64
 constexpr double kFourierFp32MinTol = 1e-6;
 
+// ---- plan cost model (MI355X) ----
+// Device time of one evaluation, per stage, fitted to stage timings measured on one
+// MI355X (uniform particles in the unit cube, N = 3e3..3e6, grids 16^3..256^3, both
+// modes; median error 3-14% per stage).  Used to choose the grid when nothing but the
+// tolerance is given: every power-of-two grid is resolved by the error split and the
+// cheapest one is taken.
+struct CostModel {
+    double pair, p2p0;          // ms per 1e9 evaluated pairs (each unordered pair once), fixed
+    double p2g, p2g_cell, p2g0; // ms per 1e9 N P^3 at full occupancy, per 1e6 cells, fixed
+    double g2p, g2p_big, g2p_cell, g2p0;
+    double fft_cell, fft0;
+    double sort, sort_cell, sort0;
+};
+constexpr CostModel kCost64 = {8.85, 0.50, 0.316, 0.205, 0.105, 1.349, 0.330, 0.153, 0.092, 0.111, 0.030,
+                               0.186, 0.011, 0.052};
+constexpr CostModel kCost32 = {6.92, 0.77, 0.386, 0.193, 0.163, 1.473, 0.0, 0.021, 0.048, 0.081, 0.038,
+                               0.208, 0.008, 0.053};
+constexpr double kWaveSlots = 1536.0;  // concurrent P2P waves at which the chip is full
+
+int p2g_blocks(const int M[3], int P)
+{
+    const int npy = std::max(1, M[1] / 8), npz = std::max(1, M[2] / 8);
+    int seg = M[0];
+    while (seg > 4 * P && (int64_t)(M[0] / seg) * npy * npz < 1024) seg >>= 1;
+    return ((M[0] + seg - 1) / seg) * npy * npz;
+}
+
+// predicted ms per stage (sort, P2P, P2G, FFT+CNV+IFFT, G2P) for n particles
+double model_ms(int mode, bool grid64, double n, const double box[3], const int M[3], int P, double rc, int B,
+                double* stage)
+{
+    const CostModel& c = (mode == EWALD_FP64) ? kCost64 : kCost32;
+    const CostModel& cf = grid64 ? kCost64 : kCost32;
+    const double V = box[0] * box[1] * box[2];
+    const double cells = (double)M[0] * M[1] * M[2];
+    const double pairs = 0.5 * n * n / V * (4.0 / 3.0) * M_PI * rc * rc * rc;
+    const double waves = n / 64.0 + 0.5 * cells / ((double)B * B * B);
+    const double np3 = n * P * P * P;
+    double st[5];
+    st[0] = c.sort * n * 1e-6 + c.sort_cell * cells * 1e-6 + c.sort0;
+    st[1] = c.pair * pairs * 1e-9 / std::min(1.0, waves / kWaveSlots) + c.p2p0;
+    st[2] = c.p2g * np3 * 1e-9 / std::min(1.0, p2g_blocks(M, P) / 1024.0) + c.p2g_cell * cells * 1e-6 + c.p2g0;
+    st[3] = cf.fft_cell * cells * 1e-6 + cf.fft0;
+    st[4] = c.g2p * np3 * 1e-9 + c.g2p_big * np3 * 1e-9 * cells * 1e-7 + c.g2p_cell * cells * 1e-6 + c.g2p0;
+    double t = 0;
+    for (int k = 0; k < 5; ++k) {
+        if (stage) stage[k] = st[k];
+        t += st[k];
+    }
+    return t;
+}
+
+// P2P tile: the smallest power of two in [2, 16] whose tiles hold about 128 particles at
+// n particles, so that the 64-target chunks of a tile are mostly full; not above any M
+int choose_tile(const double box[3], const int M[3], double n)
+{
+    const double per_cell = std::max(n, 1.0) / ((double)M[0] * M[1] * M[2]);
+    int B = 2;
+    while (B < 16 && per_cell * B * B * B < 128.0) B *= 2;
+    for (int d = 0; d < 3; ++d) B = std::min(B, M[d]);
+    (void)box;
+    return B;
+}
+
+// smallest window support meeting the window error budget (16 if none does)
+int choose_P(bool kb, double h, double xi, double budget)
+{
+    for (int P = kb ? 6 : 4; P <= 16; P += 2) {
+        const double e = kb ? err_window_kb(P, h, xi) : err_window(P, best_shape(P, h, xi), h, xi);
+        if (e <= budget) return P;
+    }
+    return 16;
+}
+
 int64_t align256(int64_t v) { return (v + 255) & ~(int64_t)255; }
 
 }  // namespace
@@ -256,19 +330,44 @@ int validate_and_resolve(const ewald_params* in, Plan* pl)
     if (grid_given) {
         for (int d = 0; d < 3; ++d) h = std::max(h, p.box[d] / p.grid[d]);
         if (!(p.xi > 0)) p.xi = xi_from_grid(h, third);
-    } else {
-        const bool xi_given = p.xi > 0;
-        if (!(p.xi > 0)) {
-            double rc = p.r_c;
-            if (!(rc > 0)) {
-                // about 300 neighbours per particle at n_max (at least 2 grid-scale cells)
-                const double V = p.box[0] * p.box[1] * p.box[2];
-                const double nmax = std::max<double>(p.n_max, 1000.0);
-                rc = std::cbrt(300.0 * V / (nmax * 4.0 / 3.0 * M_PI));
-                rc = std::min(rc, 0.45 * Lmin);
+    } else if (!(p.xi > 0) && !(p.r_c > 0)) {
+        // only the tolerance: the cheapest power-of-two grid by the cost model
+        const bool kb = (p.precision & EWALD_FLAG_WINDOW_KB) != 0;
+        const bool g64 = mode == EWALD_FP64 || p.tol < kFourierFp32MinTol;
+        const double n = (double)std::max<int64_t>(p.n_max, 1000);
+        double best = 1e300;
+        int bestM[3] = {0, 0, 0};
+        for (int m0 = 8; m0 <= 512; m0 *= 2) {
+            int M[3];
+            bool ok = true;
+            for (int d = 0; d < 3; ++d) {
+                M[d] = std::max(8, next_pow2(p.box[d] / Lmin * m0 * (1.0 - 1e-12)));
+                ok = ok && M[d] <= 512;
             }
-            p.xi = xi_from_rc(rc, third);
+            if (!ok) break;
+            double hh = 0.0, hl = 1e300;
+            for (int d = 0; d < 3; ++d) {
+                hh = std::max(hh, p.box[d] / M[d]);
+                hl = std::min(hl, p.box[d] / M[d]);
+            }
+            const double xi = xi_from_grid(hh, third);
+            const double rc = rc_from_xi(xi, third);
+            if (rc > Lmin || rc < hl || xi * rc > kScreenXmax) continue;
+            const int P = p.P > 0 ? p.P : choose_P(kb, hh, xi, third);
+            const double t = model_ms(mode, g64, n, p.box, M, P, rc, choose_tile(p.box, M, n), nullptr);
+            if (t < best) {
+                best = t;
+                for (int d = 0; d < 3; ++d) bestM[d] = M[d];
+            }
         }
+        if (!(best < 1e300)) return fail(EWALD_EUNSUPPORTED, "no grid up to 512 meets tol = %g", p.tol);
+        for (int d = 0; d < 3; ++d) p.grid[d] = bestM[d];
+        for (int d = 0; d < 3; ++d) h = std::max(h, p.box[d] / p.grid[d]);
+        p.xi = xi_from_grid(h, third);
+    } else {
+        // xi or r_c given: the grid that resolves xi (E^F = tol/3)
+        const bool xi_given = p.xi > 0;
+        if (!xi_given) p.xi = xi_from_rc(p.r_c, third);
         h = h_from_xi(p.xi, third);
         for (int d = 0; d < 3; ++d) {
             int M = next_pow2(p.box[d] / h);
@@ -296,16 +395,7 @@ int validate_and_resolve(const ewald_params* in, Plan* pl)
     // window support and shape
     const bool kb = (p.precision & EWALD_FLAG_WINDOW_KB) != 0;
     if (kb && p.P > 0 && p.P < 6) return fail(EWALD_EINVAL, "P = %d: the Kaiser-Bessel window needs P >= 6", p.P);
-    if (!(p.P > 0)) {
-        p.P = 16;
-        for (int P = kb ? 6 : 4; P <= 16; P += 2) {
-            const double e = kb ? err_window_kb(P, h, p.xi) : err_window(P, best_shape(P, h, p.xi), h, p.xi);
-            if (e <= third) {
-                p.P = P;
-                break;
-            }
-        }
-    }
+    if (!(p.P > 0)) p.P = choose_P(kb, h, p.xi, third);
     if (!(p.window_shape > 0)) p.window_shape = kb ? kb_beta_over_p(p.P, h, p.xi) : best_shape(p.P, h, p.xi);
 
     pl->p = p;
@@ -327,13 +417,7 @@ int validate_and_resolve(const ewald_params* in, Plan* pl)
         g.M[d] = p.grid[d];
         g.h[d] = p.box[d] / p.grid[d];
     }
-    // P2P tile: the smallest power of two in [2, 16] whose tiles hold about 128 particles
-    // at n_max, so that the 64-target chunks of a tile are mostly full; not above any M
-    const double cells_per_volume = (double)p.grid[0] * p.grid[1] * p.grid[2] / (p.box[0] * p.box[1] * p.box[2]);
-    const double per_cell = (double)std::max<int64_t>(p.n_max, 1) / (cells_per_volume * p.box[0] * p.box[1] * p.box[2]);
-    int B = 2;
-    while (B < 16 && per_cell * B * B * B < 128.0) B *= 2;
-    for (int d = 0; d < 3; ++d) B = std::min(B, g.M[d]);
+    const int B = choose_tile(p.box, p.grid, (double)p.n_max);
     g.B = B;
     g.log2B = ilog2(B);
     g.ncells = g.M[0] * g.M[1] * g.M[2];
@@ -363,6 +447,8 @@ int validate_and_resolve(const ewald_params* in, Plan* pl)
     info.err_window = kb ? err_window_kb(p.P, h, p.xi) : err_window(p.P, p.window_shape, h, p.xi);
     info.tile = B;
     info.workspace_bytes = layout_work(*pl, p.n_max, nullptr, nullptr);
+    info.predicted_ms = model_ms(pl->mode, pl->grid64, (double)std::max<int64_t>(p.n_max, 1), p.box, p.grid, p.P,
+                                 p.r_c, pl->g.B, nullptr);
     return EWALD_OK;
 }
 

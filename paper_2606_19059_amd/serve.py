@@ -1,7 +1,7 @@
 """Continuous-batching server for independent spectral Ewald requests on one GPU.
 
 Requests (a suspension: positions, forces, box, tolerance) arrive over time.  The server
-keeps plans (parameters and tables, keyed by box / tolerance / precision) and per-slot
+keeps plans (parameters and tables, keyed by box / tolerance / precision / size class) and per-slot
 workspaces (cell lists, grids, sorted particles) resident on the device, and admits a
 waiting request as soon as a slot is free and its HBM footprint -- workspace plus its
 input and output arrays -- fits in what the in-flight requests leave of the budget.
@@ -20,7 +20,7 @@ import time
 
 import numpy as np
 
-from . import EWALD_FP32_BULK, EWALD_FP64, Plan, resolve
+from . import Plan
 
 
 def precision_for(tol: float) -> str:
@@ -73,7 +73,7 @@ class Server:
     """Admission by HBM footprint onto a pool of streams; plans and workspaces stay resident."""
 
     def __init__(self, n_slots: int = 4, hbm_budget: int | None = None, device: str = "cuda:0",
-                 plan_n_max: int = 1 << 28):
+                 plan_n_max: int = 1 << 30):
         import torch
 
         self.device = torch.device(device)
@@ -84,29 +84,36 @@ class Server:
         self.budget = int(hbm_budget)
         self.in_flight_bytes = 0
         self.plans: dict = {}
-        self.plan_n_max = plan_n_max  # only bounds n; workspaces are sized per request
+        self.plan_n_max = plan_n_max  # largest request size served
         self.clock0 = None
         self.max_in_flight_bytes = 0  # statistics of the last run()
         self.memory_waits = 0
 
     # -- plans and footprints -------------------------------------------------------------
 
+    @staticmethod
+    def size_class(n: int) -> int:
+        """Plans are shared by requests whose n rounds up to the same power of two (>= 1024)."""
+        return max(1024, 1 << max(0, int(n) - 1).bit_length())
+
     def _key(self, job):
-        return (tuple(float(b) for b in job.box), float(job.tol), job.precision)
+        return (tuple(float(b) for b in job.box), float(job.tol), job.precision, self.size_class(job.n))
 
     def plan_for(self, job):
-        """Cached plan; plans are never replaced while the server lives (in-flight work uses them)."""
+        """Cached plan per (box, tol, precision, size class): its grid, split and cutoff come
+        from the plan cost model for that many particles.  Plans are never replaced while the
+        server lives (in-flight work uses them)."""
         key = self._key(job)
         pl = self.plans.get(key)
         if pl is None:
-            pl = Plan(job.box, job.tol, precision=job.precision, n_max=self.plan_n_max)
+            n_cls = min(self.size_class(job.n), self.plan_n_max)
+            pl = Plan(job.box, job.tol, precision=job.precision, n_max=n_cls)
             self.plans[key] = pl
         return pl
 
     def footprint(self, job) -> int:
-        """Workspace bytes + input/output arrays (3 x (3, n) float64) of a request."""
-        info = resolve(job.box, job.tol, precision=job.precision, n_max=job.n)
-        return int(info["workspace_bytes"]) + 3 * 24 * job.n
+        """Workspace bytes of the request's plan + its input/output arrays (3 x (3, n) float64)."""
+        return int(self.plan_for(job).workspace_bytes(job.n)) + 3 * 24 * job.n
 
     # -- scheduling -------------------------------------------------------------------------
 

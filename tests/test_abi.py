@@ -101,3 +101,30 @@ def test_fourier_stage_precision_follows_tolerance():
     w32 = E.resolve((1, 1, 1), 1e-6, grid=g, precision="fp32", n_max=1000)["workspace_bytes"]
     w64 = E.resolve((1, 1, 1), 1e-7, grid=g, precision="fp32", n_max=1000)["workspace_bytes"]
     assert w64 - w32 >= 0.9 * 3 * 64 ** 3 * 4  # the FP64 grid (tile tables differ slightly)
+
+
+@pytest.mark.parametrize("box,tol,prec,n", [((1, 1, 1), 1e-8, "fp64", 10**6), ((1, 1, 2), 1e-6, "fp32", 10**5),
+                                            ((1, 1, 1), 1e-4, "fp32", 3000)])
+def test_cost_model_picks_the_cheapest_resolvable_grid(box, tol, prec, n):
+    """With only the tolerance given, the plan is the grid of least predicted time among the
+    power-of-two grids (each resolved by the error split), and keeps the split."""
+    i = E.resolve(box, tol, precision=prec, n_max=n)
+    assert i["predicted_ms"] > 0
+    assert i["err_near"] <= tol / 3 * 1.0001 and i["err_far"] <= tol / 3 * 1.0001
+    m0 = min(i["grid"])
+    for m in (m0 // 2, m0 * 2):
+        if m < 8 or m * max(box) / min(box) > 512:
+            continue
+        g = tuple(int(m * b / min(box)) for b in box)
+        try:
+            j = E.resolve(box, tol, precision=prec, n_max=n, grid=g)
+        except E.EwaldError:
+            continue
+        assert j["predicted_ms"] >= i["predicted_ms"] * (1 - 1e-9), (g, j["predicted_ms"], i["predicted_ms"])
+
+
+def test_cost_model_grows_with_work():
+    a = E.resolve((1, 1, 1), 1e-6, precision="fp32", n_max=10**5, grid=(128, 128, 128))
+    b = E.resolve((1, 1, 1), 1e-6, precision="fp32", n_max=10**6, grid=(128, 128, 128))
+    c = E.resolve((1, 1, 1), 1e-8, precision="fp64", n_max=10**6, grid=(128, 128, 128))
+    assert a["predicted_ms"] < b["predicted_ms"] < c["predicted_ms"]
