@@ -232,12 +232,18 @@ def main():
     if args.cpu_seconds > 0 and not args.no_cpu_baseline:
         import oracle
 
-        # a 16-target probe sizes the timed sample to about --cpu-seconds of host work
+        # two probes (16 and 64 targets) separate the oracle's fixed cost (structure factors
+        # over all sources) from its per-target cost; they size the timed sample to about
+        # --cpu-seconds of host work
         u_np = u.cpu().numpy()
-        tc = time.perf_counter()
-        oracle.ewald_sum(x_np, f_np, wl.box, targets=W.sample_targets(wl.n, 16, seed=100 + 2))
-        probe_s = time.perf_counter() - tc
-        n_tgt = int(max(16, min(4096, 16 * args.cpu_seconds / max(probe_s, 1e-3))))
+        probe = []
+        for k in (16, 64):
+            tc = time.perf_counter()
+            oracle.ewald_sum(x_np, f_np, wl.box, targets=W.sample_targets(wl.n, k, seed=100 + 2))
+            probe.append(time.perf_counter() - tc)
+        per_target = max((probe[1] - probe[0]) / 48.0, 1e-4)
+        fixed = max(probe[0] - 16 * per_target, 0.0)
+        n_tgt = int(max(16, min(8192, (args.cpu_seconds - fixed) / per_target)))
         tgt = W.sample_targets(wl.n, n_tgt, seed=100 + 2)
         tc = time.perf_counter()
         ref = oracle.ewald_sum(x_np, f_np, wl.box, targets=tgt)

@@ -19,7 +19,8 @@ def _stream(n_req, seed):
 def _solo(job):
     from paper_2606_19059_amd import Plan, serve
 
-    pl = Plan(job.box, job.tol, precision=serve.precision_for(job.tol), n_max=1 << 28)
+    # a fresh plan with the server's parameters for this request (its size class)
+    pl = Plan(job.box, job.tol, precision=serve.precision_for(job.tol), n_max=serve.Server.size_class(job.n))
     u = pl.eval(job.x.to("cuda"), job.f.to("cuda"))
     torch.cuda.synchronize()
     return u.cpu().numpy()
