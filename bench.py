@@ -232,18 +232,13 @@ def main():
     if args.cpu_seconds > 0 and not args.no_cpu_baseline:
         import oracle
 
-        # two probes (16 and 64 targets) separate the oracle's fixed cost (structure factors
-        # over all sources) from its per-target cost; they size the timed sample to about
-        # --cpu-seconds of host work
+        # a 64-target probe sizes the timed sample to at most about --cpu-seconds of host
+        # work (its fixed cost, the structure factors over all sources, is charged per target)
         u_np = u.cpu().numpy()
-        probe = []
-        for k in (16, 64):
-            tc = time.perf_counter()
-            oracle.ewald_sum(x_np, f_np, wl.box, targets=W.sample_targets(wl.n, k, seed=100 + 2))
-            probe.append(time.perf_counter() - tc)
-        per_target = max((probe[1] - probe[0]) / 48.0, 1e-4)
-        fixed = max(probe[0] - 16 * per_target, 0.0)
-        n_tgt = int(max(16, min(8192, (args.cpu_seconds - fixed) / per_target)))
+        tc = time.perf_counter()
+        oracle.ewald_sum(x_np, f_np, wl.box, targets=W.sample_targets(wl.n, 64, seed=100 + 2))
+        probe_s = time.perf_counter() - tc
+        n_tgt = int(max(64, min(4096, 64 * args.cpu_seconds / max(probe_s, 1e-3))))
         tgt = W.sample_targets(wl.n, n_tgt, seed=100 + 2)
         tc = time.perf_counter()
         ref = oracle.ewald_sum(x_np, f_np, wl.box, targets=tgt)
@@ -264,7 +259,8 @@ def main():
     p2p_s = stages["p2p"] * 1e-3
     peak = FP64_VECTOR_TFLOPS if precision == "fp64" else FP32_VECTOR_TFLOPS
     achieved = (pairs * P2P_FLOPS_PER_PAIR / p2p_s / 1e12) if pairs else None
-    kernel = "k_p2p_sym<double>" if precision == "fp64" else "k_p2p_sym<float>"
+    kernel = ("k_p2p_sym<double, %s>" % ("true" if wl.tol >= 1e-10 else "false")) if precision == "fp64" \
+        else "k_p2p_sym<float, false>"
     roofline = {
         "kernel": kernel,
         "bound": "alu",

@@ -30,6 +30,15 @@ namespace ewald {
 
 namespace {
 
+// Reduced-cost FP64 pair formula for plans with tol >= 1e-10: degree-12 screening
+// polynomial (|dC| < 4e-12), e^{-y} from a Cody-Waite reduction and a degree-9 Taylor
+// polynomial (relative error < 7e-12 for |f| <= ln2/2; no range checks: 0 <= y < 42.3
+// on the P2P range), and one Newton step on the hardware reciprocal.
+constexpr int kExpDeg = 9;
+constexpr double kLog2e = 1.4426950408889634074;
+constexpr double kLn2Hi = 6.93147180369123816490e-01;  // ln 2 split (Cody and Waite): n ln2_hi exact
+constexpr double kLn2Lo = 1.90821492927058770002e-10;
+
 struct PairArgs {
     double xi, xi2, rc2;
     double four_xi_over_sqrtpi;
@@ -37,7 +46,9 @@ struct PairArgs {
     // screening polynomial, passed by value so that the coefficients sit in scalar
     // registers (an FMA then takes them as an operand, no per-pair register copies)
     double c64[kScreenDeg64 + 1];
+    double c64s[kScreenDeg64s + 1];
     float c32[kScreenDeg32 + 1];
+    double ec[kExpDeg + 1];  // 1/k!, Taylor coefficients of e^f
 };
 
 constexpr double kTwoOverSqrtPi = 1.1283791670955125739;
@@ -77,26 +88,41 @@ __device__ inline int lanes_below(unsigned long long m)
 }
 
 // erfcx(x) + 2x/sqrt(pi) for 0 <= x <= kScreenXmax (polynomial of screening.h)
+template <bool Fast>
 __device__ inline double screen_q64(double x, const PairArgs& a)
 {
     const double d = x + kScreenK;
     double r = __builtin_amdgcn_rcp(d);
     r = fma(fma(-d, r, 1.0), r, r);
-    r = fma(fma(-d, r, 1.0), r, r);
+    if (!Fast) r = fma(fma(-d, r, 1.0), r, r);
     const double u = fma((x - kScreenK) * r, kScreenA, kScreenB);
-    double q = a.c64[kScreenDeg64];
+    constexpr int deg = Fast ? kScreenDeg64s : kScreenDeg64;
+    const double* c = Fast ? a.c64s : a.c64;
+    double q = c[deg];
 #pragma unroll
-    for (int k = kScreenDeg64 - 1; k >= 0; --k) q = fma(q, u, a.c64[k]);
+    for (int k = deg - 1; k >= 0; --k) q = fma(q, u, c[k]);
     return fma(kTwoOverSqrtPi, x, q);
 }
 
+// e^{-y} for 0 <= y < 42.3: y = -n ln2 - f with n = rint(-y log2 e), |f| <= ln2 / 2
+__device__ inline double exp_neg_fast(double y, const PairArgs& a)
+{
+    const double n = rint(-y * kLog2e);
+    const double f = fma(n, -kLn2Lo, fma(n, -kLn2Hi, -y));
+    double p = a.ec[kExpDeg];
+#pragma unroll
+    for (int k = kExpDeg - 1; k >= 0; --k) p = fma(p, f, a.ec[k]);
+    return ldexp(p, (int)n);
+}
+
 // Coefficients of G^N(r) f = a1 f + b (r.f) r for 0 < r^2 < r_c^2 (FP64)
+template <bool Fast>
 __device__ inline void coef64(double r2, const PairArgs& a, double& a1, double& b)
 {
     const double rinv = rsqrt(r2);
     const double x = a.xi * r2 * rinv;
-    const double e = exp(-a.xi2 * r2);
-    const double C = e * screen_q64(x, a);
+    const double e = Fast ? exp_neg_fast(a.xi2 * r2, a) : exp(-a.xi2 * r2);
+    const double C = e * screen_q64<Fast>(x, a);
     a1 = fma(C, rinv, -a.four_xi_over_sqrtpi * e);
     b = C * rinv * (rinv * rinv);
 }
@@ -131,19 +157,21 @@ __device__ inline void coef32(double r2d, const PairArgs& a, float& a1, float& b
     b = C * rinv * (rinv * rinv);
 }
 
-// Pair coefficients in the formula precision TF (double: FP64 path; float: FP32 bulk).
-template <typename TF>
-__device__ inline void coef(double r2, const PairArgs& a, TF& a1, TF& b);
-template <>
-__device__ inline void coef<double>(double r2, const PairArgs& a, double& a1, double& b)
-{
-    coef64(r2, a, a1, b);
-}
-template <>
-__device__ inline void coef<float>(double r2, const PairArgs& a, float& a1, float& b)
-{
-    coef32(r2, a, a1, b);
-}
+// Pair coefficients in the formula precision TF (double: FP64 path, Fast for tol >= 1e-10;
+// float: FP32 bulk).
+template <typename TF, bool Fast>
+struct Coef;
+template <bool Fast>
+struct Coef<double, Fast> {
+    __device__ static inline void eval(double r2, const PairArgs& a, double& a1, double& b)
+    {
+        coef64<Fast>(r2, a, a1, b);
+    }
+};
+template <bool Fast>
+struct Coef<float, Fast> {
+    __device__ static inline void eval(double r2, const PairArgs& a, float& a1, float& b) { coef32(r2, a, a1, b); }
+};
 
 // c = a1 f + b (r.f) r
 template <typename TF>
@@ -160,7 +188,7 @@ constexpr int kTest = 32;    // sources tested per round (queue <= kTest * 64 pa
 
 // TF: precision of the pair formula and of the staged forces; TA: accumulator precision.
 // Positions and the r^2 < r_c^2 test are FP64 in both modes (same VALU rate as FP32).
-template <typename TF, typename TA>
+template <typename TF, typename TA, bool Fast>
 __global__ __launch_bounds__(64) void k_p2p(int n, const Rec64* __restrict__ rec,
                                             const int* __restrict__ start,
                                             const int* __restrict__ chunk_off, Geometry g,
@@ -232,7 +260,7 @@ __global__ __launch_bounds__(64) void k_p2p(int n, const Rec64* __restrict__ rec
                 const double rz = tgt[2][tt] - ring[2][slot];
                 const double r2 = rx * rx + ry * ry + rz * rz;
                 TF a1, b, c0, c1, c2;
-                coef<TF>(r2, a, a1, b);
+                Coef<TF, Fast>::eval(r2, a, a1, b);
                 apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, ringf[0][slot], ringf[1][slot], ringf[2][slot], c0, c1, c2);
                 atomicAdd(&acc[0][tt], (TA)c0);
                 atomicAdd(&acc[1][tt], (TA)c1);
@@ -339,7 +367,7 @@ __global__ void k_zero_f64(double* __restrict__ p, int64_t count)
     if (i < count) p[i] = 0.0;
 }
 
-template <typename TF>
+template <typename TF, bool Fast>
 __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__ rec,
                                                 const int* __restrict__ start,
                                                 const int* __restrict__ chunk_off, Geometry g,
@@ -418,7 +446,7 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
                 const double rz = tgt[2][tt] - ring[2][slot];
                 const double r2 = rx * rx + ry * ry + rz * rz;
                 TF a1, b, c0, c1, c2, d0, d1, d2;
-                coef<TF>(r2, a, a1, b);
+                Coef<TF, Fast>::eval(r2, a, a1, b);
                 apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, ringf[0][slot], ringf[1][slot], ringf[2][slot], c0, c1, c2);
                 apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, tgtf[0][tt], tgtf[1][tt], tgtf[2][tt], d0, d1, d2);
                 atomicAdd(&acc[0][tt], (double)c0);
@@ -541,7 +569,14 @@ hipError_t launch_p2p(const Plan& pl, const Work& w, int n, hipStream_t s)
     a.four_xi_over_sqrtpi = 4.0 * pl.xi / sqrt(M_PI);
     a.xi2_log2e = a.xi2 * 1.4426950408889634;
     for (int k = 0; k <= kScreenDeg64; ++k) a.c64[k] = kScreenC64[k];
+    for (int k = 0; k <= kScreenDeg64s; ++k) a.c64s[k] = kScreenC64s[k];
     for (int k = 0; k <= kScreenDeg32; ++k) a.c32[k] = (float)kScreenC32[k];
+    double fact = 1.0;
+    for (int k = 0; k <= kExpDeg; ++k) {
+        a.ec[k] = 1.0 / fact;
+        fact *= (double)(k + 1);
+    }
+    const bool fast = pl.p.tol >= 1e-10;
     const int64_t waves = (int64_t)pl.g.ntiles + (n + kWave - 1) / kWave;
     const dim3 grid((unsigned)waves), block(kWave);
     const Rec64* rec = (const Rec64*)w.rec;
@@ -549,21 +584,27 @@ hipError_t launch_p2p(const Plan& pl, const Work& w, int n, hipStream_t s)
     if (pl.deterministic) {
         // FP32 bulk accumulates in FP64 as well: LDS atomic adds of FP64 are fast on
         // gfx950, those of FP32 are not (measured: 3x slower kernel)
-        if (f64)
-            hipLaunchKernelGGL((k_p2p<double, double>), grid, block, 0, s, n, rec, w.start, w.chunk_off, pl.g,
-                               a, w.u_near);
+        if (f64 && fast)
+            hipLaunchKernelGGL((k_p2p<double, double, true>), grid, block, 0, s, n, rec, w.start, w.chunk_off,
+                               pl.g, a, w.u_near);
+        else if (f64)
+            hipLaunchKernelGGL((k_p2p<double, double, false>), grid, block, 0, s, n, rec, w.start, w.chunk_off,
+                               pl.g, a, w.u_near);
         else
-            hipLaunchKernelGGL((k_p2p<float, double>), grid, block, 0, s, n, rec, w.start, w.chunk_off, pl.g,
-                               a, w.u_near);
+            hipLaunchKernelGGL((k_p2p<float, double, false>), grid, block, 0, s, n, rec, w.start, w.chunk_off,
+                               pl.g, a, w.u_near);
         return hipGetLastError();
     }
     const int64_t cnt = 3 * (int64_t)n;
     hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, w.u_near, cnt);
-    if (f64)
-        hipLaunchKernelGGL((k_p2p_sym<double>), grid, block, 0, s, n, rec, w.start, w.chunk_off, pl.g, a,
+    if (f64 && fast)
+        hipLaunchKernelGGL((k_p2p_sym<double, true>), grid, block, 0, s, n, rec, w.start, w.chunk_off, pl.g, a,
+                           w.u_near);
+    else if (f64)
+        hipLaunchKernelGGL((k_p2p_sym<double, false>), grid, block, 0, s, n, rec, w.start, w.chunk_off, pl.g, a,
                            w.u_near);
     else
-        hipLaunchKernelGGL((k_p2p_sym<float>), grid, block, 0, s, n, rec, w.start, w.chunk_off, pl.g, a,
+        hipLaunchKernelGGL((k_p2p_sym<float, false>), grid, block, 0, s, n, rec, w.start, w.chunk_off, pl.g, a,
                            w.u_near);
     return hipGetLastError();
 }

@@ -1,8 +1,9 @@
 """Parity at the benchmark's full size, in the configuration bench.py times.
 
 N = 1e6 uniform particles, tol 1e-8, 128^3 grid, FP64: the oracle evaluates sampled
-targets one by one (all N sources).  The P2P stage is compared exactly (same xi, r_c)
-and the full result within tol.
+targets one by one (all N sources).  The P2P stage is compared at the same xi, r_c within
+the bound of the plan's pair formula (1e-10; the reduced-cost formula of tol >= 1e-10), and
+the full result within tol.
 """
 import numpy as np
 import pytest
@@ -33,9 +34,9 @@ def test_c2_full_size_meets_tolerance(c2):
     torch.cuda.synchronize()
     tgt = W.sample_targets(wl.n, 16, seed=102)
     u_np, un_np = u.cpu().numpy(), un.cpu().numpy()
-    # P2P stage exactly: the oracle's real-space sum at the plan's xi and r_c
+    # P2P stage: the oracle's real-space sum at the plan's xi and r_c
     rn = oracle.real_space(x, f, wl.box, plan.info["xi"], plan.info["r_c"], targets=tgt)
-    assert np.max(np.abs(un_np[:, tgt] - rn)) < 1e-12 * np.max(np.abs(rn))
+    assert np.max(np.abs(un_np[:, tgt] - rn)) < 1e-10 * np.max(np.abs(rn))
     # the whole evaluation against the classical Ewald sum
     ref = oracle.ewald_sum(x, f, wl.box, targets=tgt)
     err = oracle.rel_err(u_np[:, tgt], ref)

@@ -2,7 +2,11 @@
 
 All calls go through the C ABI (``libewald.so``).  Tolerances (FP64 path):
 * P2G grid, far grid, P2P sum, far field: 1e-12 relative to the array's max -- the two
-  sides compute the same discrete sums in FP64 with different summation orders;
+  sides compute the same discrete sums in FP64 with different summation orders (stage
+  plans are made with tol < 1e-10, which selects the full-precision pair formula);
+* the reduced-cost pair formula of plans with tol >= 1e-10: its own error bound (screening
+  polynomial |dC| < 4e-12, exponential relative error < 7e-12, so each pair term is within
+  ~1.2e-11 of exact; tested at 1e-10 relative to the array's max);
 * the full evaluation against the classical Ewald oracle: the requested tol (relative RMS).
 """
 import math
@@ -49,9 +53,10 @@ CASES = {
 }
 
 
-def make_plan(E, name, n_max, **kw):
+def make_plan(E, name, n_max, tol=1e-11, **kw):
+    """Plan with the case's explicit parameters; tol < 1e-10 selects the full-precision formula."""
     box, grid, xi, rc, P, m = CASES[name]
-    return E.Plan(box, 1e-6, xi=xi, r_c=rc, grid=grid, P=P, window_shape=m, n_max=n_max, **kw)
+    return E.Plan(box, tol, xi=xi, r_c=rc, grid=grid, P=P, window_shape=m, n_max=n_max, **kw)
 
 
 def test_tiny_eval_runs():
@@ -97,6 +102,20 @@ def test_near_and_far_fields_match_oracle(name, n):
     un, uf = host(un), host(uf)
     assert maxrel(un, oracle.real_space(x, f, box, xi, rc)) < 1e-12
     assert maxrel(uf, S.far_field(x, f, box, grid, xi, P, m)) < 1e-11
+
+
+@pytest.mark.parametrize("name,n", [("cube32_P8", 2000), ("aniso_P12", 1531)])
+def test_reduced_cost_pair_formula_within_its_bound(name, n):
+    """Plans with tol >= 1e-10 use the shorter pair formula; the P2P sum stays within its bound."""
+    E = _E()
+    box, grid, xi, rc, P, m = CASES[name]
+    pl = make_plan(E, name, n, tol=1e-6)
+    x, f = W.particles(n, box, seed=19)
+    un, _ = pl.eval_parts(dev(x), dev(f))
+    ref = oracle.real_space(x, f, box, xi, rc)
+    err = maxrel(host(un), ref)
+    print("%s: reduced-cost P2P max rel error %.2e" % (name, err))
+    assert err < 1e-10
 
 
 def test_full_eval_matches_spectral_oracle():

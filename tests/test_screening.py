@@ -20,7 +20,7 @@ def _consts():
     src = open(HDR).read()
     scal = dict(re.findall(r"constexpr double (kScreen[A-Za-z]+) = ([^;]+);", src))
     arrs = {k: [float(v) for v in body.split(",")]
-            for k, body in re.findall(r"constexpr double (kScreenC\d+)\[\d+\] = \{([^}]*)\};", src)}
+            for k, body in re.findall(r"constexpr double (kScreenC\w+)\[\d+\] = \{([^}]*)\};", src)}
     return {k: float(v) for k, v in scal.items()}, arrs
 
 
@@ -40,6 +40,8 @@ def test_screening_polynomials_meet_their_bounds():
     x = np.linspace(0.0, X, 2601)
     ref = np.array([float(mp.erfc(v) + 2 * v * mp.exp(-v * v) / mp.sqrt(mp.pi)) for v in map(mp.mpf, x)])
     e64 = np.max(np.abs(_eval(x, arrs["kScreenC64"], K, A, B) - ref))
+    e64s = np.max(np.abs(_eval(x, arrs["kScreenC64s"], K, A, B) - ref))
     e32 = np.max(np.abs(_eval(x, arrs["kScreenC32"], K, A, B) - ref))
     assert e64 < 5e-15, e64
+    assert e64s < 5e-12, e64s
     assert e32 < 2e-9, e32
