@@ -53,6 +53,8 @@ def _load():
         lib.ewo_real_space.argtypes = [i64, dp, dp, i64, ip, dp, ctypes.c_double, ctypes.c_double, dp]
         lib.ewo_recip.argtypes = [i64, dp, dp, i64, ip, dp, ctypes.c_double, ctypes.c_double, dp]
         lib.ewo_direct_sphere.argtypes = [i64, dp, dp, dp, ctypes.c_double, dp]
+        lib.ewo_real_space_st.argtypes = [i64, dp, dp, i64, ip, dp, ctypes.c_double, ctypes.c_double, dp]
+        lib.ewo_recip_st.argtypes = [i64, dp, dp, i64, ip, dp, ctypes.c_double, ctypes.c_double, dp]
         lib.ewo_num_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -138,6 +140,47 @@ def direct_sphere(x, f, L, R):
     return u
 
 
+def stresslet_tensor(q, nrm):
+    """S_j = q_j n_j^T as 9 rows: S[3 b + c, j] = q_bj n_cj."""
+    q = np.asarray(q, dtype=np.float64)
+    nrm = np.asarray(nrm, dtype=np.float64)
+    return np.ascontiguousarray(np.einsum("bj,cj->bcj", q, nrm).reshape(9, -1))
+
+
+def real_space_st(x, S, L, xi, r_cut, targets=None):
+    """Near-field stresslet sum (screened T^N over all images with 0 < |r| < r_cut) for the
+    source tensors S (9, n).  Returns (3, n_targets)."""
+    lib = _load()
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    L = np.ascontiguousarray(np.broadcast_to(np.asarray(L, dtype=np.float64), (3,)))
+    n = x.shape[1]
+    assert S.shape == (9, n)
+    t, tp = _targets(targets)
+    nt = n if t is None else t.shape[0]
+    u = np.zeros((3, nt), dtype=np.float64)
+    if n == 0 or nt == 0:
+        return u
+    lib.ewo_real_space_st(n, _dptr(x), _dptr(S), nt, tp, _dptr(L), float(xi), float(r_cut), _dptr(u))
+    return u
+
+
+def recip_space_st(x, S, L, xi, k_max, targets=None):
+    """Fourier-space stresslet sum over k != 0, |k| <= k_max.  Returns (3, n_targets)."""
+    lib = _load()
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    L = np.ascontiguousarray(np.broadcast_to(np.asarray(L, dtype=np.float64), (3,)))
+    n = x.shape[1]
+    t, tp = _targets(targets)
+    nt = n if t is None else t.shape[0]
+    u = np.zeros((3, nt), dtype=np.float64)
+    if n == 0 or nt == 0:
+        return u
+    lib.ewo_recip_st(n, _dptr(x), _dptr(S), nt, tp, _dptr(L), float(xi), float(k_max), _dptr(u))
+    return u
+
+
 def default_xi(L, n, n_targets=None):
     """Oracle's own split parameter: real-space radius r_o = 6/xi_o.
 
@@ -151,12 +194,13 @@ def default_xi(L, n, n_targets=None):
     return 12.0 / Lmin
 
 
-def ewald_sum(x, f, L, targets=None, xi=None, parts=False):
+def ewald_sum(x, f, L, targets=None, xi=None, parts=False, q=None, nrm=None):
     """The periodic Stokeslet sum by classical Ewald summation, FP64, ~1e-13 accurate.
 
     xi_o is the oracle's own split parameter (the result does not depend on it);
-    r_cut = 6/xi_o and k_max = 12 xi_o put both truncations below 1e-15.
-    Returns (3, n_targets), or (total, real, recip, self) when ``parts``.
+    r_cut = 6/xi_o and k_max = 12 xi_o put both truncations below 1e-15.  With ``q`` and
+    ``nrm`` (3, n) the stresslet sources q n^T of the combined single and double layer sum
+    (Sec. 2.2) are added.  Returns (3, n_targets), or (total, real, recip, self) when ``parts``.
     """
     x, f, L = _prep(x, f, L)
     n = x.shape[1]
@@ -168,6 +212,10 @@ def ewald_sum(x, f, L, targets=None, xi=None, parts=False):
     ur = real_space(x, f, L, xi, r_cut, targets)
     uk = recip_space(x, f, L, xi, k_max, targets)
     us = self_term(f, xi, targets)
+    if q is not None:
+        S = stresslet_tensor(q, nrm)
+        ur = ur + real_space_st(x, S, L, xi, r_cut, targets)
+        uk = uk + recip_space_st(x, S, L, xi, k_max, targets)
     tot = ur + uk + us
     if parts:
         return tot, ur, uk, us

@@ -293,3 +293,160 @@ void ewo_direct_sphere(int64_t n, const double* x, const double* f, const double
         u[2 * n + i] = s2;
     }
 }
+
+/* ---------------------------------------------------------------------------
+ * Stresslet (double-layer) sources, Sec. 2.2 "Combined single and double layers":
+ * each source j also carries vectors q_j, n_j, and
+ *
+ *     u_a(x_i) += sum_j sum_p' T_abc(x_i - x_j + p) q_jb n_jc,
+ *     T_abc(r) = -6 r_a r_b r_c / |r|^5,
+ *
+ * written here with the source tensor S_j = q_j n_j^T given as 9 rows
+ * S[(3 b + c) n + j].  The split uses the same screening as the Stokeslet's:
+ * T^F has the Fourier transform That(k) (1 + k^2/(4 xi^2)) e^{-k^2/(4 xi^2)} with
+ *     That_abc(k) = (8 pi i / k^4) (k^2 (delta_bc k_a + delta_ab k_c + delta_ac k_b) - 2 k_a k_b k_c),
+ * and the real-space remainder (derived in the design notes from T = -2 d_a d_b d_c |r|
+ * + 2 (delta_bc d_a + delta_ab d_c + delta_ac d_b) |r|^{-1}, with the Hasimoto split of
+ * |r| and of 1/|r|) is
+ *     T^N_abc(r) = A(r) rh_a rh_b rh_c + B(r) (delta_ab rh_c + delta_ac rh_b + delta_bc rh_a),
+ *     A = -2 (3 erfc(xi r) / r^2 + (6 xi / (sqrt(pi) r) + 4 xi^3 r / sqrt(pi)) e^{-xi^2 r^2}),
+ *     B = 4 xi^3 r e^{-xi^2 r^2} / sqrt(pi),      rh = r / |r|.
+ * T^F is odd, so the far field needs no self correction.
+ */
+void ewo_real_space_st(int64_t n, const double* x, const double* S, int64_t nt, const int64_t* tidx,
+                       const double L[3], double xi, double r_cut, double* u)
+{
+    double* xw = (double*)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    ewo_wrap(n, x, L, xw);
+    const double rc2 = r_cut * r_cut;
+    const double sqrtpi = sqrt(EWO_PI);
+    const int64_t ntt = tidx ? nt : n;
+
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t t = 0; t < ntt; ++t) {
+        const int64_t i = tidx ? tidx[t] : t;
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int64_t j = 0; j < n; ++j) {
+            const double d[3] = {xw[i] - xw[j], xw[n + i] - xw[n + j], xw[2 * n + i] - xw[2 * n + j]};
+            int lo[3], hi[3];
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = (int)ceil((-r_cut - d[a]) / L[a]);
+                hi[a] = (int)floor((r_cut - d[a]) / L[a]);
+            }
+            double Sj[3][3];
+            for (int b = 0; b < 3; ++b)
+                for (int c = 0; c < 3; ++c) Sj[b][c] = S[(3 * b + c) * n + j];
+            for (int m0 = lo[0]; m0 <= hi[0]; ++m0)
+                for (int m1 = lo[1]; m1 <= hi[1]; ++m1)
+                    for (int m2 = lo[2]; m2 <= hi[2]; ++m2) {
+                        const double rv[3] = {d[0] + m0 * L[0], d[1] + m1 * L[1], d[2] + m2 * L[2]};
+                        const double rr = rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2];
+                        if (!(rr < rc2) || rr == 0.0) continue;
+                        const double r = sqrt(rr);
+                        const double e = exp(-xi * xi * rr);
+                        const double A = -2.0 * (3.0 * erfc(xi * r) / rr + (6.0 * xi / (sqrtpi * r) +
+                                                                           4.0 * xi * xi * xi * r / sqrtpi) * e);
+                        const double B = 4.0 * xi * xi * xi * r * e / sqrtpi;
+                        const double rh[3] = {rv[0] / r, rv[1] / r, rv[2] / r};
+                        for (int a = 0; a < 3; ++a)
+                            for (int b = 0; b < 3; ++b)
+                                for (int c = 0; c < 3; ++c) {
+                                    const double T = A * rh[a] * rh[b] * rh[c] +
+                                                     B * ((a == b) * rh[c] + (a == c) * rh[b] + (b == c) * rh[a]);
+                                    acc[a] += T * Sj[b][c];
+                                }
+                    }
+        }
+        for (int a = 0; a < 3; ++a) u[a * ntt + t] = acc[a];
+    }
+    free(xw);
+}
+
+/*
+ * Fourier-space stresslet sum on the 3-periodic lattice (k != 0, |k| <= k_max):
+ *   u_a(x_i) = (1/V) sum_k Re{ e^{i k.x_i} That^F_abc(k) Shat_bc(k) },  Shat(k) = sum_j S_j e^{-i k.x_j},
+ * with That^F = i A(k) P_abc(k), A = 8 pi / k^4 (1 + k^2/(4 xi^2)) e^{-k^2/(4 xi^2)},
+ * P_abc = k^2 (delta_bc k_a + delta_ab k_c + delta_ac k_b) - 2 k_a k_b k_c (real); over the
+ * half space with a factor 2 (the k and -k terms are complex conjugates).
+ */
+void ewo_recip_st(int64_t n, const double* x, const double* S, int64_t nt, const int64_t* tidx,
+                  const double L[3], double xi, double k_max, double* u)
+{
+    const int64_t ntt = tidx ? nt : n;
+    const double V = L[0] * L[1] * L[2];
+    const int nk[3] = {(int)floor(k_max * L[0] / (2.0 * EWO_PI)), (int)floor(k_max * L[1] / (2.0 * EWO_PI)),
+                       (int)floor(k_max * L[2] / (2.0 * EWO_PI))};
+    const double km2 = k_max * k_max;
+    const double inv4xi2 = 1.0 / (4.0 * xi * xi);
+    int64_t cap = (int64_t)(nk[0] + 1) * (2 * nk[1] + 1) * (2 * nk[2] + 1);
+    double* kv = (double*)malloc(sizeof(double) * 4 * (size_t)cap);
+    int64_t K = 0;
+    for (int a = 0; a <= nk[0]; ++a)
+        for (int b = -nk[1]; b <= nk[1]; ++b)
+            for (int c = -nk[2]; c <= nk[2]; ++c) {
+                if (a == 0 && (b < 0 || (b == 0 && c <= 0))) continue;
+                const double k0 = 2.0 * EWO_PI * a / L[0], k1 = 2.0 * EWO_PI * b / L[1], k2 = 2.0 * EWO_PI * c / L[2];
+                const double kk = k0 * k0 + k1 * k1 + k2 * k2;
+                if (kk > km2) continue;
+                kv[4 * K] = k0;
+                kv[4 * K + 1] = k1;
+                kv[4 * K + 2] = k2;
+                kv[4 * K + 3] = 8.0 * EWO_PI / (kk * kk) * (1.0 + kk * inv4xi2) * exp(-kk * inv4xi2);
+                ++K;
+            }
+    /* structure factors Shat_bc(k): 9 complex numbers per k, summed per thread */
+    int nth = ewo_num_threads();
+    double* Sloc = (double*)calloc((size_t)nth * (size_t)K * 18, sizeof(double));
+#pragma omp parallel
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double* Sh = Sloc + (size_t)tid * (size_t)K * 18;
+#pragma omp for schedule(static)
+        for (int64_t j = 0; j < n; ++j) {
+            for (int64_t q = 0; q < K; ++q) {
+                const double ph = kv[4 * q] * x[j] + kv[4 * q + 1] * x[n + j] + kv[4 * q + 2] * x[2 * n + j];
+                const double re = cos(ph), im = -sin(ph);
+                for (int bc = 0; bc < 9; ++bc) {
+                    const double s = S[bc * n + j];
+                    Sh[18 * q + 2 * bc] += s * re;
+                    Sh[18 * q + 2 * bc + 1] += s * im;
+                }
+            }
+        }
+    }
+    for (int t = 1; t < nth; ++t) {
+        const double* src = Sloc + (size_t)t * (size_t)K * 18;
+        for (int64_t q = 0; q < 18 * K; ++q) Sloc[q] += src[q];
+    }
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t t = 0; t < ntt; ++t) {
+        const int64_t i = tidx ? tidx[t] : t;
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int64_t q = 0; q < K; ++q) {
+            const double k[3] = {kv[4 * q], kv[4 * q + 1], kv[4 * q + 2]};
+            const double Ak = kv[4 * q + 3];
+            const double kk = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+            const double* sh = Sloc + 18 * q;
+            const double ph = k[0] * x[i] + k[1] * x[n + i] + k[2] * x[2 * n + i];
+            const double cph = cos(ph), sph = sin(ph);
+            for (int a = 0; a < 3; ++a) {
+                double wr = 0.0, wi = 0.0; /* w_a = P_abc Shat_bc */
+                for (int b = 0; b < 3; ++b)
+                    for (int c = 0; c < 3; ++c) {
+                        const double P = kk * ((b == c) * k[a] + (a == b) * k[c] + (a == c) * k[b]) -
+                                         2.0 * k[a] * k[b] * k[c];
+                        wr += P * sh[2 * (3 * b + c)];
+                        wi += P * sh[2 * (3 * b + c) + 1];
+                    }
+                /* Re{ e^{i ph} i A w } = -A (cos(ph) wi + sin(ph) wr) */
+                acc[a] += -Ak * (cph * wi + sph * wr);
+            }
+        }
+        for (int a = 0; a < 3; ++a) u[a * ntt + t] = 2.0 * acc[a] / V;
+    }
+    free(Sloc);
+    free(kv);
+}

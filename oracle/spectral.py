@@ -33,7 +33,7 @@ import math
 import numpy as np
 from scipy.special import i0 as _i0
 
-from . import real_space, self_term, wrap
+from . import real_space, real_space_st, self_term, stresslet_tensor, wrap
 
 
 def window_1d(dist, h, P, m, window="gaussian"):
@@ -141,6 +141,41 @@ def cnv(phihat, L, M, xi, P, m, window="gaussian"):
     )
 
 
+def cnv_stresslet(shat, L, M, xi, P, m, window="gaussian"):
+    """The stresslet part of the combined CNV (Sec. 2.2, combined layers): 9 grid components in,
+    3 out, vhat_a(k) = i A(k) / what(k)^2 P_abc(k) Shat_bc(k) with A = 8 pi / k^4 (1 + k^2/4 xi^2)
+    e^{-k^2/4 xi^2} and P_abc = k^2 (delta_bc k_a + delta_ab k_c + delta_ac k_b) - 2 k_a k_b k_c.
+    ``shat``: (9, M1, M2, M3) complex, row 3 b + c.  Zeroes k = 0 and the Nyquist planes."""
+    ns, ks = wave_numbers(L, M)
+    kv = [ks[0][:, None, None], ks[1][None, :, None], ks[2][None, None, :]]
+    kk = kv[0] ** 2 + kv[1] ** 2 + kv[2] ** 2
+    with np.errstate(divide="ignore", invalid="ignore"):
+        A = 8.0 * math.pi / (kk * kk) * (1.0 + kk / (4.0 * xi * xi)) * np.exp(-kk / (4.0 * xi * xi))
+    what = (
+        window_hat_1d(ks[0], L[0], M[0], P, m, window)[:, None, None]
+        * window_hat_1d(ks[1], L[1], M[1], P, m, window)[None, :, None]
+        * window_hat_1d(ks[2], L[2], M[2], P, m, window)[None, None, :]
+    )
+    scale = A / (what * what)
+    bad = kk == 0.0
+    for d in range(3):
+        nyq = np.zeros(int(M[d]), dtype=bool)
+        nyq[int(M[d]) // 2] = True
+        shape = [1, 1, 1]
+        shape[d] = int(M[d])
+        bad = bad | nyq.reshape(shape)
+    scale = np.where(bad, 0.0, scale)
+    out = []
+    for a in range(3):
+        w = 0.0
+        for b in range(3):
+            for c in range(3):
+                Pabc = kk * ((b == c) * kv[a] + (a == b) * kv[c] + (a == c) * kv[b]) - 2.0 * kv[a] * kv[b] * kv[c]
+                w = w + Pabc * shat[3 * b + c]
+        out.append(1j * scale * w)
+    return np.stack(out)
+
+
 def g2p(v, x, L, M, P, m, chunk=4096, window="gaussian"):
     """eq. (g2p): u(x_i) = h1 h2 h3 sum_l w(x_i - g_l + p) v(g_l).  Returns (3, n)."""
     x = wrap(np.asarray(x, dtype=np.float64), L)
@@ -169,19 +204,40 @@ def far_grid(x, f, L, M, xi, P, m, window="gaussian"):
     return np.real(np.fft.ifftn(vhat, axes=(1, 2, 3)))
 
 
+def far_grid_combined(x, f, S, L, M, xi, P, m, window="gaussian"):
+    """Combined single and double layer far grid: 3 + 9 components through P2G and the FFT,
+    CNV maps them to 3, then the IFFT."""
+    phi = p2g(x, f, L, M, P, m, window=window)
+    sphi = np.concatenate([p2g(x, S[3 * r:3 * r + 3], L, M, P, m, window=window) for r in range(3)])
+    vhat = cnv(np.fft.fftn(phi, axes=(1, 2, 3)), L, M, xi, P, m, window) + \
+        cnv_stresslet(np.fft.fftn(sphi, axes=(1, 2, 3)), L, M, xi, P, m, window)
+    return np.real(np.fft.ifftn(vhat, axes=(1, 2, 3)))
+
+
 def far_field(x, f, L, M, xi, P, m, window="gaussian"):
     """u^F_h at every particle: G2P(IFFT(CNV(FFT(P2G(f))))).  Returns (3, n)."""
     v = far_grid(x, f, L, M, xi, P, m, window)
     return g2p(v, x, L, M, P, m, window=window)
 
 
-def spectral_ewald(x, f, L, M, xi, r_c, P, m, parts=False, window="gaussian"):
-    """Algorithm "se": u_h = u^N + u^F_h, plus the self term -(4 xi/sqrt(pi)) f.
+def far_field_combined(x, f, S, L, M, xi, P, m, window="gaussian"):
+    """u^F_h of the combined single and double layer sources at every particle."""
+    return g2p(far_grid_combined(x, f, S, L, M, xi, P, m, window), x, L, M, P, m, window=window)
+
+
+def spectral_ewald(x, f, L, M, xi, r_c, P, m, parts=False, window="gaussian", q=None, nrm=None):
+    """Algorithm "se": u_h = u^N + u^F_h, plus the self term -(4 xi/sqrt(pi)) f (the stresslet
+    part, with ``q`` and ``nrm``, needs none: T^F is odd).
 
     Returns (3, n), or (total, near, far, self) when ``parts``.
     """
-    un = real_space(x, f, L, xi, r_c)
-    uf = far_field(x, f, L, M, xi, P, m, window)
+    if q is not None:
+        S = stresslet_tensor(q, nrm)
+        un = real_space(x, f, L, xi, r_c) + real_space_st(x, S, L, xi, r_c)
+        uf = far_field_combined(x, f, S, L, M, xi, P, m, window)
+    else:
+        un = real_space(x, f, L, xi, r_c)
+        uf = far_field(x, f, L, M, xi, P, m, window)
     us = self_term(f, xi)
     tot = un + uf + us
     if parts:

@@ -285,3 +285,95 @@ def test_kaiser_bessel_far_field_converges():
     errs = [oracle.rel_err(S.far_field(x, f, L, (32, 32, 32), xi, P, 0, window="kb"), ref) for P in (4, 6, 8)]
     assert errs[0] > errs[1] > errs[2]
     assert errs[2] < 1e-6
+
+
+# ---------------------------------------------------------------- stresslet (double layer) sources
+
+
+def _stresslet_inputs(n, box, seed, orthogonal=False):
+    rng = np.random.default_rng(seed)
+    x = rng.random((3, n)) * np.asarray(box, dtype=float)[:, None]
+    q = rng.standard_normal((3, n))
+    nr = rng.standard_normal((3, n))
+    if orthogonal:
+        nr -= q * (np.sum(q * nr, 0) / np.sum(q * q, 0))
+    return x, q, nr
+
+
+@pytest.mark.parametrize("box", [(1.0, 1.0, 1.0), (1.0, 0.8, 1.7)])
+def test_stresslet_sum_is_independent_of_xi(box):
+    """The combined single and double layer sum does not depend on the split parameter: T^N
+    and That^F (and G^N, Ghat^F) are two halves of one kernel only if they match."""
+    x, q, nr = _stresslet_inputs(40, box, seed=21)
+    f = np.random.default_rng(22).standard_normal((3, 40))
+    lmin = min(box)
+    us = [oracle.ewald_sum(x, f, box, xi=c / lmin, q=q, nrm=nr) for c in (5.0, 8.0, 12.0)]
+    for u in us[1:]:
+        assert oracle.max_rel_err(u, us[0]) < 1e-11
+
+
+def test_stresslet_matches_finite_differences_of_stokeslets():
+    """For q . n = 0, T_abc q_b n_c = (n.grad)(G q) + (q.grad)(G n) (T = d_c G_ab + d_b G_ac
+    + 2 delta_bc d_a |r|^-1), so each stresslet equals the limit of four point forces +-q/eps
+    at y -+ eps n/2 and +-n/eps at y -+ eps q/2.  Pins the stresslet oracle against the
+    (independently pinned) Stokeslet oracle at spectator points; the error falls as eps^2."""
+    box = (1.0, 1.0, 1.3)
+    ns, nt = 12, 6
+    ys, q, nr = _stresslet_inputs(ns, box, seed=7, orthogonal=True)
+    xs = np.random.default_rng(8).random((3, nt)) * np.asarray(box)[:, None]
+    x_all = np.concatenate([ys, xs], 1)
+    z = np.zeros((3, nt))
+    u_st = oracle.ewald_sum(x_all, np.zeros_like(x_all), box, q=np.concatenate([q, z], 1),
+                            nrm=np.concatenate([nr, z], 1))[:, ns:]
+    errs = []
+    for eps in (1e-3, 1e-4):
+        pos, frc = [], []
+        for j in range(ns):
+            for a, b in ((nr[:, j], q[:, j]), (q[:, j], nr[:, j])):
+                pos += [ys[:, j] - 0.5 * eps * a, ys[:, j] + 0.5 * eps * a]
+                frc += [b / eps, -b / eps]
+        X = np.concatenate([np.array(pos).T, xs], 1)
+        F = np.concatenate([np.array(frc).T, z], 1)
+        errs.append(oracle.max_rel_err(oracle.ewald_sum(X, F, box)[:, 4 * ns:], u_st))
+    assert errs[1] < 2e-6
+    assert 50 < errs[0] / errs[1] < 200  # second order in eps
+
+
+def test_stresslet_near_field_tends_to_the_bare_kernel():
+    """As xi -> 0 the screened T^N tends to T = -6 r r r / r^5; checked against a direct image
+    sum of T written out here."""
+    box = (1.0, 1.0, 1.0)
+    x, q, nr = _stresslet_inputs(7, box, seed=5)
+    S = oracle.stresslet_tensor(q, nr)
+    rc = 0.9
+    un = oracle.real_space_st(x, S, box, 1e-7, rc)
+    ref = np.zeros((3, 7))
+    for i in range(7):
+        for j in range(7):
+            for m in np.ndindex(3, 3, 3):
+                r = x[:, i] - x[:, j] + (np.array(m) - 1) * np.asarray(box)
+                d = np.linalg.norm(r)
+                if d == 0 or d >= rc:
+                    continue
+                Sj = S[:, j].reshape(3, 3)
+                ref[:, i] += -6.0 * r * (r @ Sj @ r) / d**5
+    assert oracle.max_rel_err(un, ref) < 1e-9
+
+
+@pytest.mark.parametrize("window", ["gaussian", "kb"])
+def test_spectral_combined_far_field_converges_to_direct_fourier_sum(window):
+    """P2G of the 3 + 9 components, FFT, combined CNV (12 -> 3), IFFT, G2P converges to the
+    classical Fourier sums of both kernels as the window support grows."""
+    box = (1.0, 1.0, 1.0)
+    x, q, nr = _stresslet_inputs(60, box, seed=3)
+    f = np.random.default_rng(4).standard_normal((3, 60))
+    St = oracle.stresslet_tensor(q, nr)
+    xi = 8.0
+    ref = oracle.recip_space_st(x, St, box, xi, 12 * xi) + oracle.recip_space(x, f, box, xi, 12 * xi)
+    errs = []
+    for P in (6, 10, 14):
+        m = 0 if window == "kb" else 0.95 * math.sqrt(math.pi * P)
+        errs.append(oracle.rel_err(S.far_field_combined(x, f, St, box, (32, 32, 32), xi, P, m,
+                                                               window=window), ref))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < (1e-11 if window == "kb" else 1e-8)
