@@ -64,11 +64,15 @@ enum {
     EWALD_FLAG_STAGE_TIMERS = 1 << 9, /* record per-stage HIP events (see ewald_stage_ms) */
     EWALD_FLAG_WINDOW_KB = 1 << 10,   /* truncated Kaiser-Bessel window (Sec. 2.2) instead of the
                                          Gaussian: w0(d) = I0(beta sqrt(1 - (2d/(P h))^2)) / I0(beta) */
-    EWALD_FLAG_DETERMINISTIC = 1 << 11 /* bitwise reproducible results: P2P evaluates every pair
+    EWALD_FLAG_DETERMINISTIC = 1 << 11, /* bitwise reproducible results: P2P evaluates every pair
                                           from both sides (about twice the pair work).  Without it
                                           each pair is evaluated once and its two contributions
                                           are added with atomics, so repeated evaluations agree to
                                           rounding (~1e-16 relative), not bitwise */
+    EWALD_FLAG_STRESSLET = 1 << 12     /* the plan also evaluates stresslet (double-layer) sources
+                                          with ewald_eval_combined: its workspace holds the sorted
+                                          source tensors and a 9-component grid.  Not combinable
+                                          with EWALD_FLAG_DETERMINISTIC (EWALD_EUNSUPPORTED) */
 };
 
 /*
@@ -141,6 +145,27 @@ int64_t ewald_workspace_bytes(ewald_plan_t plan, int64_t n);
  */
 int ewald_eval(ewald_plan_t plan, int64_t n, const double* x, const double* f, double* u,
                void* workspace, int64_t workspace_bytes, void* stream);
+
+/*
+ * Combined single and double layer sources (Sec. 2.2, "Combined single and double
+ * layers"): every particle j carries a force f_j and two vectors q_j, n_j, and
+ *   u(x_i) = sum_j sum_p' [ G(x_i - x_j + p) f_j + T(x_i - x_j + p) (q_j n_j^T) ]
+ * with the stresslet T_abc(r) = -6 r_a r_b r_c / |r|^5 (component a of T (q n^T) is
+ * sum_bc T_abc q_b n_c).  Split like the Stokeslet: T^N in P2P, That^F (the same
+ * screening (1 + k^2/(4 xi^2)) e^{-k^2/(4 xi^2)}) through P2G (force + the 6 independent
+ * components of (q n^T + n q^T)/2, T being symmetric), FFT, CNV (9 -> 3 components),
+ * IFFT and G2P; T^F is odd, so there is no stresslet self term.  x, f, q, nrm: (3, n) FP64
+ * device inputs; u: (3, n) FP64 device output.  The plan must carry
+ * EWALD_FLAG_STRESSLET (else EWALD_EINVAL); other errors as ewald_eval.  The split
+ * parameters are those of the Stokeslet error model.
+ */
+int ewald_eval_combined(ewald_plan_t plan, int64_t n, const double* x, const double* f, const double* q,
+                        const double* nrm, double* u, void* workspace, int64_t workspace_bytes, void* stream);
+
+/* Near and far parts of ewald_eval_combined (as ewald_eval_parts). */
+int ewald_eval_combined_parts(ewald_plan_t plan, int64_t n, const double* x, const double* f, const double* q,
+                              const double* nrm, double* u_near, double* u_far, void* workspace,
+                              int64_t workspace_bytes, void* stream);
 
 /*
  * Diagnostic split of ewald_eval: u_near = the P2P sum (Sec. 2.1,

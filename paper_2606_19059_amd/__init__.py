@@ -26,6 +26,7 @@ EWALD_FLAG_P2P_FP64_ACC = 1 << 8
 EWALD_FLAG_STAGE_TIMERS = 1 << 9
 EWALD_FLAG_WINDOW_KB = 1 << 10
 EWALD_FLAG_DETERMINISTIC = 1 << 11
+EWALD_FLAG_STRESSLET = 1 << 12
 
 STAGES = ("sort", "p2p", "p2g", "fgc", "g2p", "total")
 
@@ -38,6 +39,8 @@ EXPORTS = (
     "ewald_workspace_bytes",
     "ewald_eval",
     "ewald_eval_parts",
+    "ewald_eval_combined",
+    "ewald_eval_combined_parts",
     "ewald_spread",
     "ewald_far_grid",
     "ewald_stage_ms",
@@ -107,6 +110,9 @@ def load(path: str | None = None):
     lib.ewald_workspace_bytes.restype = i64
     for name in ("ewald_eval", "ewald_eval_parts"):
         getattr(lib, name).argtypes = [vp, i64, vp, vp, vp] + ([vp] if name == "ewald_eval_parts" else []) + [vp, i64, vp]
+    for name in ("ewald_eval_combined", "ewald_eval_combined_parts"):
+        getattr(lib, name).argtypes = [vp, i64, vp, vp, vp, vp, vp] + (
+            [vp] if name == "ewald_eval_combined_parts" else []) + [vp, i64, vp]
     for name in ("ewald_spread", "ewald_far_grid"):
         getattr(lib, name).argtypes = [vp, i64, vp, vp, vp, vp, i64, vp]
     lib.ewald_stage_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32]
@@ -148,7 +154,8 @@ def _check_particles(x, f):
 
 
 def make_params(box, tol, xi=None, r_c=None, grid=None, P=None, precision="fp64", n_max=1 << 20,
-                window_shape=None, p2p_fp64_acc=False, timers=False, window="gaussian", deterministic=False):
+                window_shape=None, p2p_fp64_acc=False, timers=False, window="gaussian", deterministic=False,
+                stresslet=False):
     """The ewald_params struct for these arguments (None = derive from tol)."""
     p = Params()
     for d in range(3):
@@ -163,7 +170,7 @@ def make_params(box, tol, xi=None, r_c=None, grid=None, P=None, precision="fp64"
         raise ValueError("window must be 'gaussian' or 'kb'")
     p.precision = mode | (EWALD_FLAG_P2P_FP64_ACC if p2p_fp64_acc else 0) | (
         EWALD_FLAG_STAGE_TIMERS if timers else 0) | (EWALD_FLAG_WINDOW_KB if window == "kb" else 0) | (
-        EWALD_FLAG_DETERMINISTIC if deterministic else 0)
+        EWALD_FLAG_DETERMINISTIC if deterministic else 0) | (EWALD_FLAG_STRESSLET if stresslet else 0)
     p.reserved = 0
     p.n_max = int(n_max)
     p.window_shape = float(window_shape) if window_shape else 0.0
@@ -182,6 +189,7 @@ def _info_dict(info, precision):
         "predicted_ms": info.predicted_ms,
         "window": "kb" if q.precision & EWALD_FLAG_WINDOW_KB else "gaussian",
         "deterministic": bool(q.precision & EWALD_FLAG_DETERMINISTIC),
+        "stresslet": bool(q.precision & EWALD_FLAG_STRESSLET),
     }
 
 
@@ -202,10 +210,11 @@ class Plan:
     """
 
     def __init__(self, box, tol, xi=None, r_c=None, grid=None, P=None, precision="fp64", n_max=1 << 20,
-                 window_shape=None, p2p_fp64_acc=False, timers=False, window="gaussian", deterministic=False):
+                 window_shape=None, p2p_fp64_acc=False, timers=False, window="gaussian", deterministic=False,
+                 stresslet=False):
         lib = load()
         p = make_params(box, tol, xi, r_c, grid, P, precision, n_max, window_shape, p2p_fp64_acc, timers,
-                        window, deterministic)
+                        window, deterministic, stresslet)
         h = ctypes.c_void_p()
         _check(lib.ewald_plan_create(ctypes.byref(p), ctypes.byref(h)))
         self._h = h
@@ -265,6 +274,35 @@ class Plan:
         wp, wb = self._ws_args(n, workspace, x.device)
         _check(load().ewald_eval_parts(self._h, n, _ptr(x), _ptr(f), _ptr(un), _ptr(uf), wp, wb,
                                        _stream_handle(stream)))
+        return un, uf
+
+    def eval_combined(self, x, f, q, nrm, out=None, workspace=None, stream=None):
+        """u (3, n): Stokeslet forces f plus stresslet sources q n^T at every particle
+        (plan created with ``stresslet=True``)."""
+        import torch
+
+        n = _check_particles(x, f)
+        _check_particles(q, nrm)
+        if q.shape != x.shape:
+            raise ValueError("q and nrm must have the shape of x")
+        u = out if out is not None else torch.empty_like(x)
+        wp, wb = self._ws_args(n, workspace, x.device)
+        _check(load().ewald_eval_combined(self._h, n, _ptr(x), _ptr(f), _ptr(q), _ptr(nrm), _ptr(u), wp, wb,
+                                          _stream_handle(stream)))
+        return u
+
+    def eval_combined_parts(self, x, f, q, nrm, workspace=None, stream=None):
+        """(u_near, u_far) of eval_combined."""
+        import torch
+
+        n = _check_particles(x, f)
+        _check_particles(q, nrm)
+        if q.shape != x.shape:
+            raise ValueError("q and nrm must have the shape of x")
+        un, uf = torch.empty_like(x), torch.empty_like(x)
+        wp, wb = self._ws_args(n, workspace, x.device)
+        _check(load().ewald_eval_combined_parts(self._h, n, _ptr(x), _ptr(f), _ptr(q), _ptr(nrm), _ptr(un),
+                                                _ptr(uf), wp, wb, _stream_handle(stream)))
         return un, uf
 
     def _grid_call(self, fn, x, f, workspace, stream):

@@ -287,7 +287,8 @@ int64_t layout_work(const Plan& pl, int64_t n, char* base, Work* w)
     o->part = (int*)take(4 * (int64_t)scan_part_elems(std::max(g.ncells, g.ntiles)));
     o->rec = (void*)take((int64_t)recsz * nn);
     o->u_near = (double*)take(8 * 3 * nn);
-    o->grid = (void*)take((int64_t)real * 3 * g.ncells);
+    o->srec = pl.stresslet ? (double*)take(8 * 6 * nn) : nullptr;
+    o->grid = (void*)take((int64_t)real * (pl.stresslet ? 9 : 3) * g.ncells);
     o->bytes = off;
     return off;
 }
@@ -311,8 +312,12 @@ int validate_and_resolve(const ewald_params* in, Plan* pl)
     if (mode != EWALD_FP64 && mode != EWALD_FP32_BULK)
         return fail(EWALD_EINVAL, "unknown precision mode %d", mode);
     if (p.precision &
-        ~(0xff | EWALD_FLAG_P2P_FP64_ACC | EWALD_FLAG_STAGE_TIMERS | EWALD_FLAG_WINDOW_KB | EWALD_FLAG_DETERMINISTIC))
+        ~(0xff | EWALD_FLAG_P2P_FP64_ACC | EWALD_FLAG_STAGE_TIMERS | EWALD_FLAG_WINDOW_KB | EWALD_FLAG_DETERMINISTIC |
+          EWALD_FLAG_STRESSLET))
         return fail(EWALD_EINVAL, "unknown precision flags 0x%x", p.precision);
+    if ((p.precision & EWALD_FLAG_STRESSLET) && (p.precision & EWALD_FLAG_DETERMINISTIC))
+        return fail(EWALD_EUNSUPPORTED, "stresslet sources are evaluated by the symmetric P2P only "
+                                        "(EWALD_FLAG_DETERMINISTIC not available with EWALD_FLAG_STRESSLET)");
     if (mode == EWALD_FP32_BULK && p.tol < 1e-7)
         return fail(EWALD_EUNSUPPORTED, "tol = %g below 1e-7 needs the FP64 mode", p.tol);
     const bool grid_given = p.grid[0] > 0 && p.grid[1] > 0 && p.grid[2] > 0;
@@ -403,6 +408,7 @@ int validate_and_resolve(const ewald_params* in, Plan* pl)
     pl->grid64 = mode == EWALD_FP64 || p.tol < kFourierFp32MinTol;
     pl->fp64acc = true;  // FP64 near-field accumulation in both modes (EWALD_FLAG_P2P_FP64_ACC is implied)
     pl->deterministic = (p.precision & EWALD_FLAG_DETERMINISTIC) != 0;
+    pl->stresslet = (p.precision & EWALD_FLAG_STRESSLET) != 0;
     pl->timers = (p.precision & EWALD_FLAG_STAGE_TIMERS) != 0;
     pl->P = p.P;
     pl->window_kb = kb;
@@ -584,9 +590,16 @@ int check_eval_args(ewald_plan_t plan, int64_t n, const void* x, const void* f, 
 enum class Out { Full, Parts, Spread, FarGrid };
 
 int run(ewald_plan_t plan, int64_t n64, const double* x, const double* f, void* o1, void* o2, void* ws,
-        int64_t wsb, void* stream, Out what)
+        int64_t wsb, void* stream, Out what, const double* q = nullptr, const double* nrm = nullptr)
 {
     Work w;
+    const bool st = q != nullptr || nrm != nullptr;
+    if (st) {
+        if (!plan) return fail(EWALD_EINVAL, "null plan");
+        if (!reinterpret_cast<const Plan*>(plan)->stresslet)
+            return fail(EWALD_EINVAL, "stresslet sources need a plan created with EWALD_FLAG_STRESSLET");
+        if (n64 > 0 && (!q || !nrm)) return fail(EWALD_EINVAL, "null stresslet vector pointer");
+    }
     int rc = check_eval_args(plan, n64, x, f, o1, what == Out::Parts ? o2 : o1, ws, wsb, &w);
     if (rc != EWALD_OK || n64 == 0) return rc;
     Plan* pl = reinterpret_cast<Plan*>(plan);
@@ -599,19 +612,20 @@ int run(ewald_plan_t plan, int64_t n64, const double* x, const double* f, void* 
     };
     mark(0);
     if ((e = launch_sort(*pl, w, n, x, f, s)) != hipSuccess) return hip_fail(e, "sort");
+    if (st && (e = launch_gather_st(*pl, w, n, q, nrm, s)) != hipSuccess) return hip_fail(e, "stresslet gather");
     mark(1);
     if (what == Out::Full || what == Out::Parts) {
-        if ((e = launch_p2p(*pl, w, n, s)) != hipSuccess) return hip_fail(e, "P2P");
+        if ((e = launch_p2p(*pl, w, n, s, st)) != hipSuccess) return hip_fail(e, "P2P");
     }
     mark(2);
-    if ((e = launch_p2g(*pl, w, n, s)) != hipSuccess) return hip_fail(e, "P2G");
+    if ((e = launch_p2g(*pl, w, n, s, st)) != hipSuccess) return hip_fail(e, "P2G");
     mark(3);
     const size_t gbytes = (size_t)3 * pl->g.ncells * (pl->grid64 ? 8 : 4);
     if (what == Out::Spread) {
         e = hipMemcpyAsync(o1, w.grid, gbytes, hipMemcpyDeviceToDevice, s);
         return e == hipSuccess ? EWALD_OK : hip_fail(e, "grid copy");
     }
-    if ((e = launch_fgc(*pl, w, s, true, true)) != hipSuccess) return hip_fail(e, "FFT/CNV/IFFT");
+    if ((e = launch_fgc(*pl, w, s, true, true, st)) != hipSuccess) return hip_fail(e, "FFT/CNV/IFFT");
     mark(4);
     if (what == Out::FarGrid) {
         e = hipMemcpyAsync(o1, w.grid, gbytes, hipMemcpyDeviceToDevice, s);
@@ -705,6 +719,21 @@ int ewald_eval_parts(ewald_plan_t plan, int64_t n, const double* x, const double
                      double* u_far, void* workspace, int64_t workspace_bytes, void* stream)
 {
     return run(plan, n, x, f, u_near, u_far, workspace, workspace_bytes, stream, Out::Parts);
+}
+
+int ewald_eval_combined(ewald_plan_t plan, int64_t n, const double* x, const double* f, const double* q,
+                        const double* nrm, double* u, void* workspace, int64_t workspace_bytes, void* stream)
+{
+    if (!q && !nrm) return fail(EWALD_EINVAL, "null stresslet vector pointer");
+    return run(plan, n, x, f, u, u, workspace, workspace_bytes, stream, Out::Full, q, nrm);
+}
+
+int ewald_eval_combined_parts(ewald_plan_t plan, int64_t n, const double* x, const double* f, const double* q,
+                              const double* nrm, double* u_near, double* u_far, void* workspace,
+                              int64_t workspace_bytes, void* stream)
+{
+    if (!q && !nrm) return fail(EWALD_EINVAL, "null stresslet vector pointer");
+    return run(plan, n, x, f, u_near, u_far, workspace, workspace_bytes, stream, Out::Parts, q, nrm);
 }
 
 int ewald_spread(ewald_plan_t plan, int64_t n, const double* x, const double* f, void* grid, void* workspace,

@@ -277,6 +277,79 @@ __global__ __launch_bounds__(256) void k_fft_x_cnv(T* __restrict__ grid, int64_t
     }
 }
 
+// ---- pass 3 for combined single and double layer sources ----
+// The 9 components (force 0-2, symmetric stresslet tensor 3-8: xx, yy, zz, xy, xz, yz) have
+// been transformed along x (k_fft_x_cnv without CNV).  Per x-column batch: CNV 9 -> 3 in
+// FP64 (Sec. 2.2, combined layers),
+//   vhat_a = A(k) [ (k^2 phi_a - k_a (k.phi)) + i (k^2 (k_a tr S + 2 (S k)_a) - 2 k_a (k.S k)) ],
+// the first term Ghat^F, the second That^F of the stresslet (That_abc = (8 pi i / k^4)
+// (k^2 (delta_bc k_a + delta_ab k_c + delta_ac k_b) - 2 k_a k_b k_c), contracted with the
+// symmetric S), A = 8 pi / k^4 (1 + k^2/(4 xi^2)) e^{-k^2/(4 xi^2)} / what^2 with the DFT and
+// h^3 scales folded in; then the inverse x transform of the 3 results.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cnv_st_x(T* __restrict__ grid, int64_t ncells, int M1, int M2, int H,
+                                                  int ncols, const C2<T>* __restrict__ tw, CnvArgs ca)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const int per = M1 * ncols;
+    C2<T>* a = reinterpret_cast<C2<T>*>(smem_raw);
+    C2<T>* b = a + (size_t)3 * per;
+    const int tiles_per_y = H / ncols;
+    const int ky = blockIdx.x / tiles_per_y;
+    const int kz0 = (blockIdx.x - ky * tiles_per_y) * ncols;
+    const int64_t rowstride = (int64_t)M2 * H;
+    const int kys = (ky < M2 / 2) ? ky : ky - M2;
+    const double k1 = ca.twopi_over_L[1] * kys;
+    const double e1 = ca.E1[ky];
+    for (int idx = threadIdx.x; idx < per; idx += blockDim.x) {
+        const int kx = idx / ncols, c = idx - kx * ncols;
+        const int kz = kz0 + c;
+        const int kxs = (kx < M1 / 2) ? kx : kx - M1;
+        const double k0 = ca.twopi_over_L[0] * kxs;
+        const double k2 = ca.twopi_over_L[2] * kz;
+        const double K2 = k0 * k0 + k1 * k1 + k2 * k2;
+        double A = 0.0;
+        if (K2 > 0.0) A = ca.E0[kx] * e1 * ca.E2[kz] * ca.eightpi * (1.0 + K2 * ca.inv4xi2) / (K2 * K2);
+        const int64_t off = (int64_t)kx * rowstride + (int64_t)ky * H + kz;
+        double vr[9], vi[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const C2<T> v = reinterpret_cast<const C2<T>*>(grid + q * ncells)[off];
+            vr[q] = v.x;
+            vi[q] = v.y;
+        }
+        // Stokeslet part
+        const double dr = k0 * vr[0] + k1 * vr[1] + k2 * vr[2];
+        const double di = k0 * vi[0] + k1 * vi[1] + k2 * vi[2];
+        // stresslet part: S k, k.S k, tr S (complex)
+        const double skr0 = vr[3] * k0 + vr[6] * k1 + vr[7] * k2, ski0 = vi[3] * k0 + vi[6] * k1 + vi[7] * k2;
+        const double skr1 = vr[6] * k0 + vr[4] * k1 + vr[8] * k2, ski1 = vi[6] * k0 + vi[4] * k1 + vi[8] * k2;
+        const double skr2 = vr[7] * k0 + vr[8] * k1 + vr[5] * k2, ski2 = vi[7] * k0 + vi[8] * k1 + vi[5] * k2;
+        const double ksk_r = k0 * skr0 + k1 * skr1 + k2 * skr2, ksk_i = k0 * ski0 + k1 * ski1 + k2 * ski2;
+        const double tr_r = vr[3] + vr[4] + vr[5], tr_i = vi[3] + vi[4] + vi[5];
+        const double kk[3] = {k0, k1, k2};
+        const double skr[3] = {skr0, skr1, skr2}, ski[3] = {ski0, ski1, ski2};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double wr = K2 * (kk[d] * tr_r + 2.0 * skr[d]) - 2.0 * kk[d] * ksk_r;
+            const double wi = K2 * (kk[d] * tr_i + 2.0 * ski[d]) - 2.0 * kk[d] * ksk_i;
+            // (K2 phi_d - k_d (k.phi)) + i w
+            const double re = K2 * vr[d] - kk[d] * dr - wi;
+            const double im = K2 * vi[d] - kk[d] * di + wr;
+            a[(size_t)d * per + idx] = C2<T>{(T)(A * re), (T)(A * im)};
+        }
+    }
+    __syncthreads();
+    C2<T>* r = lds_fft<T>(a, b, M1, ncols, 3, +1, tw);
+    const int tot = 3 * per;
+    for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+        const int comp = idx / per, rem = idx - comp * per;
+        const int e = rem / ncols, c = rem - e * ncols;
+        C2<T>* data = reinterpret_cast<C2<T>*>(grid + comp * ncells);
+        data[(int64_t)e * rowstride + (int64_t)ky * H + kz0 + c] = r[idx];
+    }
+}
+
 inline int pow2_floor(int v)
 {
     int p = 1;
@@ -285,7 +358,7 @@ inline int pow2_floor(int v)
 }
 
 template <typename T>
-hipError_t launch_fgc_t(const Plan& pl, const Work& w, hipStream_t s, bool inverse_too, bool cnv)
+hipError_t launch_fgc_t(const Plan& pl, const Work& w, hipStream_t s, bool inverse_too, bool cnv, bool st)
 {
     const Geometry& g = pl.g;
     const int M1 = g.M[0], M2 = g.M[1], M3 = g.M[2], H = M3 / 2;
@@ -303,14 +376,16 @@ hipError_t launch_fgc_t(const Plan& pl, const Work& w, hipStream_t s, bool inver
     int ncz = pow2_floor(max(1, budget / H));
     if (ncz > nlines) ncz = pow2_floor(nlines);
     size_t shz = 2 * (size_t)H * ncz * sizeof(C2<T>);
-    dim3 gz((nlines + ncz - 1) / ncz, 3);
+    const int ncomp_in = st ? 9 : 3;  // forward transforms: force (+ stresslet tensor)
+    dim3 gz((nlines + ncz - 1) / ncz, ncomp_in);
     hipLaunchKernelGGL((k_fft_z<T>), gz, dim3(256), shz, s, grid, nc, nlines, H, ncz, -1, twh, twf);
     // pass 2: y forward
     int ncy = pow2_floor(max(1, budget / M2));
     if (ncy > H) ncy = H;
     size_t shy = 2 * (size_t)M2 * ncy * sizeof(C2<T>);
-    dim3 gy(M1 * (H / ncy), 3);
+    dim3 gy(M1 * (H / ncy), ncomp_in);
     hipLaunchKernelGGL((k_fft_y<T>), gy, dim3(256), shy, s, grid, nc, M2, H, ncy, -1, tw1);
+    gy.y = 3;  // the inverse transforms carry the 3 velocity components
     // pass 3: x forward + CNV (+ inverse)
     int ncx = pow2_floor(max(1, budget / (3 * M1)));
     if (ncx > H) ncx = H;
@@ -322,8 +397,19 @@ hipError_t launch_fgc_t(const Plan& pl, const Work& w, hipStream_t s, bool inver
     ca.E0 = pl.d_cnv[0];
     ca.E1 = pl.d_cnv[1];
     ca.E2 = pl.d_cnv[2];
-    hipLaunchKernelGGL((k_fft_x_cnv<T>), dim3(M2 * (H / ncx)), dim3(256), shx, s, grid, nc, M1, M2, H, ncx,
-                       cnv ? 1 : 0, inverse_too ? 1 : 0, tw0, ca);
+    if (st) {
+        // forward x transforms of the 9 components, three at a time; then CNV 9 -> 3 and the
+        // inverse x transform
+        for (int grp = 0; grp < 3; ++grp)
+            hipLaunchKernelGGL((k_fft_x_cnv<T>), dim3(M2 * (H / ncx)), dim3(256), shx, s,
+                               grid + (int64_t)3 * grp * nc, nc, M1, M2, H, ncx, 0, 0, tw0, ca);
+        if (cnv && inverse_too)
+            hipLaunchKernelGGL((k_cnv_st_x<T>), dim3(M2 * (H / ncx)), dim3(256), shx, s, grid, nc, M1, M2, H, ncx,
+                               tw0, ca);
+    } else {
+        hipLaunchKernelGGL((k_fft_x_cnv<T>), dim3(M2 * (H / ncx)), dim3(256), shx, s, grid, nc, M1, M2, H, ncx,
+                           cnv ? 1 : 0, inverse_too ? 1 : 0, tw0, ca);
+    }
     if (inverse_too) {
         hipLaunchKernelGGL((k_fft_y<T>), gy, dim3(256), shy, s, grid, nc, M2, H, ncy, +1, tw1);
         hipLaunchKernelGGL((k_fft_z<T>), gz, dim3(256), shz, s, grid, nc, nlines, H, ncz, +1, twh, twf);
@@ -333,10 +419,10 @@ hipError_t launch_fgc_t(const Plan& pl, const Work& w, hipStream_t s, bool inver
 
 }  // namespace
 
-hipError_t launch_fgc(const Plan& pl, const Work& w, hipStream_t s, bool inverse_too, bool cnv)
+hipError_t launch_fgc(const Plan& pl, const Work& w, hipStream_t s, bool inverse_too, bool cnv, bool st)
 {
-    if (pl.grid64) return launch_fgc_t<double>(pl, w, s, inverse_too, cnv);
-    return launch_fgc_t<float>(pl, w, s, inverse_too, cnv);
+    if (pl.grid64) return launch_fgc_t<double>(pl, w, s, inverse_too, cnv, st);
+    return launch_fgc_t<float>(pl, w, s, inverse_too, cnv, st);
 }
 
 }  // namespace ewald

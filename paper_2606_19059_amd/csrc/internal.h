@@ -76,6 +76,7 @@ struct Plan {
     bool grid64;           // grid, FFT, CNV, IFFT in FP64 (always in FP64 mode)
     bool fp64acc;          // FP32 bulk: FP64 near-field accumulation
     bool deterministic;    // bitwise reproducible P2P (one-sided pair evaluation)
+    bool stresslet;        // workspace sized for combined Stokeslet + stresslet sources
     bool timers;
     int device;
     // device tables owned by the plan
@@ -101,7 +102,10 @@ struct Work {
     int* part;       // scan partials
     void* rec;       // [n] Rec64, sorted order
     double* u_near;  // [3][n] near field, sorted order
-    void* grid;      // 3 x ncells reals (double or float), then the in-place half spectrum
+    double* srec;    // [n][6] symmetric stresslet tensors (xx, yy, zz, xy, xz, yz), sorted order
+                     // (stresslet plans only)
+    void* grid;      // 3 (9 for stresslet plans) x ncells reals (double or float), then the
+                     // in-place half spectrum
     int64_t bytes;
 };
 
@@ -110,9 +114,12 @@ int64_t layout_work(const Plan& pl, int64_t n, char* base, Work* w);
 // Launchers (all enqueue on `s`, return hipSuccess or the launch error).
 hipError_t launch_sort(const Plan& pl, const Work& w, int n, const double* x, const double* f,
                        hipStream_t s);
-hipError_t launch_p2p(const Plan& pl, const Work& w, int n, hipStream_t s);
-hipError_t launch_p2g(const Plan& pl, const Work& w, int n, hipStream_t s);
-hipError_t launch_fgc(const Plan& pl, const Work& w, hipStream_t s, bool inverse_too, bool cnv);
+// `st`: this evaluation has stresslet sources (w.srec filled, 9 grid components)
+hipError_t launch_gather_st(const Plan& pl, const Work& w, int n, const double* q, const double* nrm,
+                            hipStream_t s);
+hipError_t launch_p2p(const Plan& pl, const Work& w, int n, hipStream_t s, bool st);
+hipError_t launch_p2g(const Plan& pl, const Work& w, int n, hipStream_t s, bool st);
+hipError_t launch_fgc(const Plan& pl, const Work& w, hipStream_t s, bool inverse_too, bool cnv, bool st);
 hipError_t launch_g2p(const Plan& pl, const Work& w, int n, const double* f, double* u,
                       double* u_near_out, double* u_far_out, hipStream_t s);
 hipError_t launch_fill_i32(int* p, int64_t count, int value, hipStream_t s);

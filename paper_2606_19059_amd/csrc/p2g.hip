@@ -35,6 +35,7 @@ template <typename T, typename TG, int P>
 __global__ __launch_bounds__(kWaves * 64) void k_p2g_sweep(const typename RecView<T>::Rec* __restrict__ rec,
                                                            const int* __restrict__ start, Geometry g,
                                                            WinArgs<T> wa, int seg, int npy, int npz,
+                                                           const double* __restrict__ sv, int sv_off,
                                                            TG* __restrict__ grid)
 {
     constexpr int W = kPatch + P - 1;
@@ -113,6 +114,10 @@ __global__ __launch_bounds__(kWaves * 64) void k_p2g_sweep(const typename RecVie
                 int c[3];
                 T t[3], f[3];
                 RecView<T>::load(rec[p], g, c, t, f);
+                if (sv) {  // spread three stresslet components instead of the force
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) f[d] = (T)sv[6 * (int64_t)p + sv_off + d];
+                }
                 const int iy = r / nzs, zs = r - iy * nzs;
                 const int oy = iy - (P - 1);  // stencil anchor - y0
                 const int czu = (zt0 + zs) * B + (c[2] & (B - 1));
@@ -184,7 +189,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_p2g_sweep(const typename RecVie
 
 
 template <typename TG, int P>
-hipError_t launch_p2g_t(const Plan& pl, const Work& w, hipStream_t s)
+hipError_t launch_p2g_t(const Plan& pl, const Work& w, hipStream_t s, bool st)
 {
     const Geometry& g = pl.g;
     const int npy = g.M[1] / kPatch, npz = g.M[2] / kPatch;
@@ -194,22 +199,26 @@ hipError_t launch_p2g_t(const Plan& pl, const Work& w, hipStream_t s)
     while (seg > 4 * P && (int64_t)(g.M[0] / seg) * npy * npz < 1024) seg >>= 1;
     const int nseg = (g.M[0] + seg - 1) / seg;
     const int blocks = nseg * npy * npz;
-    hipLaunchKernelGGL((k_p2g_sweep<double, TG, P>), dim3(blocks), dim3(kWaves * kWave), 0, s, (const Rec64*)w.rec,
-                       w.start, g, make_win_args<double>(pl), seg, npy, npz, (TG*)w.grid);
+    // force (3 components); with stresslet sources also the 6 tensor components, three per sweep
+    const int passes = st ? 3 : 1;
+    for (int ps = 0; ps < passes; ++ps)
+        hipLaunchKernelGGL((k_p2g_sweep<double, TG, P>), dim3(blocks), dim3(kWaves * kWave), 0, s,
+                           (const Rec64*)w.rec, w.start, g, make_win_args<double>(pl), seg, npy, npz,
+                           ps == 0 ? nullptr : w.srec, 3 * (ps - 1), (TG*)w.grid + (int64_t)3 * ps * g.ncells);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_p2g_p(const Plan& pl, const Work& w, hipStream_t s)
+hipError_t launch_p2g_p(const Plan& pl, const Work& w, hipStream_t s, bool st)
 {
     switch (pl.P) {
-    case 4: return launch_p2g_t<T, 4>(pl, w, s);
-    case 6: return launch_p2g_t<T, 6>(pl, w, s);
-    case 8: return launch_p2g_t<T, 8>(pl, w, s);
-    case 10: return launch_p2g_t<T, 10>(pl, w, s);
-    case 12: return launch_p2g_t<T, 12>(pl, w, s);
-    case 14: return launch_p2g_t<T, 14>(pl, w, s);
-    case 16: return launch_p2g_t<T, 16>(pl, w, s);
+    case 4: return launch_p2g_t<T, 4>(pl, w, s, st);
+    case 6: return launch_p2g_t<T, 6>(pl, w, s, st);
+    case 8: return launch_p2g_t<T, 8>(pl, w, s, st);
+    case 10: return launch_p2g_t<T, 10>(pl, w, s, st);
+    case 12: return launch_p2g_t<T, 12>(pl, w, s, st);
+    case 14: return launch_p2g_t<T, 14>(pl, w, s, st);
+    case 16: return launch_p2g_t<T, 16>(pl, w, s, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -218,11 +227,11 @@ hipError_t launch_p2g_p(const Plan& pl, const Work& w, hipStream_t s)
 
 int p2g_max_runs() { return kMaxRuns; }
 
-hipError_t launch_p2g(const Plan& pl, const Work& w, int n, hipStream_t s)
+hipError_t launch_p2g(const Plan& pl, const Work& w, int n, hipStream_t s, bool st)
 {
     (void)n;
-    if (pl.grid64) return launch_p2g_p<double>(pl, w, s);
-    return launch_p2g_p<float>(pl, w, s);
+    if (pl.grid64) return launch_p2g_p<double>(pl, w, s, st);
+    return launch_p2g_p<float>(pl, w, s, st);
 }
 
 }  // namespace ewald

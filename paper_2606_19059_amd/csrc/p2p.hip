@@ -49,6 +49,7 @@ struct PairArgs {
     double c64s[kScreenDeg64s + 1];
     float c32[kScreenDeg32 + 1];
     double ec[kExpDeg + 1];  // 1/k!, Taylor coefficients of e^f
+    double six_xi_over_sqrtpi, four_xi3_over_sqrtpi;  // stresslet screening
 };
 
 constexpr double kTwoOverSqrtPi = 1.1283791670955125739;
@@ -172,6 +173,81 @@ template <bool Fast>
 struct Coef<float, Fast> {
     __device__ static inline void eval(double r2, const PairArgs& a, float& a1, float& b) { coef32(r2, a, a1, b); }
 };
+
+// Stresslet pair (combined single and double layer sources, Sec. 2.2): with the screened
+// remainder of T(r) = -6 r r r / |r|^5,
+//   T^N_abc(r) S_bc = alpha r_a (r.S r) + beta (2 (S r)_a + tr(S) r_a)   (S symmetric),
+//   alpha = -2 |r|^-3 (3 erfc(xi |r|) |r|^-2 + e^{-xi^2 r^2} (6 xi/(sqrt(pi) |r|) + 4 xi^3 |r|/sqrt(pi))),
+//   beta = 4 xi^3 e^{-xi^2 r^2} / sqrt(pi).
+// Both follow from the same exponential and screening polynomial as G^N:
+// erfc(x) = C - (2x/sqrt(pi)) e^{-x^2}.
+template <bool Fast>
+__device__ inline void coef64_st(double r2, const PairArgs& a, double& a1, double& b, double& al, double& be)
+{
+    const double rinv = rsqrt(r2);
+    const double r = r2 * rinv;
+    const double x = a.xi * r;
+    const double e = Fast ? exp_neg_fast(a.xi2 * r2, a) : exp(-a.xi2 * r2);
+    const double C = e * screen_q64<Fast>(x, a);
+    const double rinv2 = rinv * rinv, rinv3 = rinv2 * rinv;
+    a1 = fma(C, rinv, -a.four_xi_over_sqrtpi * e);
+    b = C * rinv3;
+    const double erfc_x = fma(-kTwoOverSqrtPi * x, e, C);
+    al = -2.0 * rinv3 * fma(3.0 * erfc_x, rinv2, e * fma(a.six_xi_over_sqrtpi, rinv, a.four_xi3_over_sqrtpi * r));
+    be = a.four_xi3_over_sqrtpi * e;
+}
+
+__device__ inline void coef32_st(double r2d, const PairArgs& a, float& a1, float& b, float& al, float& be)
+{
+    const float r2 = (float)r2d;
+    const float y = __builtin_amdgcn_rsqf(r2);
+    const float rinv = y * fmaf(-0.5f * r2 * y, y, 1.5f);
+    const float r = r2 * rinv;
+    const float x = (float)a.xi * r;
+    const double ea = -a.xi2_log2e * r2d;
+    const double en = rint(ea);
+    const float e = ldexpf(__builtin_amdgcn_exp2f((float)(ea - en)), (int)en);
+    const float C = e * screen_q32(x, a);
+    const float rinv2 = rinv * rinv, rinv3 = rinv2 * rinv;
+    a1 = fmaf(C, rinv, -(float)a.four_xi_over_sqrtpi * e);
+    b = C * rinv3;
+    const float erfc_x = fmaf(-(float)kTwoOverSqrtPi * x, e, C);
+    al = -2.0f * rinv3 *
+         fmaf(3.0f * erfc_x, rinv2, e * fmaf((float)a.six_xi_over_sqrtpi, rinv, (float)a.four_xi3_over_sqrtpi * r));
+    be = (float)a.four_xi3_over_sqrtpi * e;
+}
+
+template <typename TF, bool Fast>
+struct CoefSt;
+template <bool Fast>
+struct CoefSt<double, Fast> {
+    __device__ static inline void eval(double r2, const PairArgs& a, double& a1, double& b, double& al, double& be)
+    {
+        coef64_st<Fast>(r2, a, a1, b, al, be);
+    }
+};
+template <bool Fast>
+struct CoefSt<float, Fast> {
+    __device__ static inline void eval(double r2, const PairArgs& a, float& a1, float& b, float& al, float& be)
+    {
+        coef32_st(r2, a, a1, b, al, be);
+    }
+};
+
+// c += alpha r (r.S r) + beta (2 S r + tr(S) r), S = (s0..s5) = (xx, yy, zz, xy, xz, yz)
+template <typename TF>
+__device__ inline void apply_st(TF al, TF be, TF rx, TF ry, TF rz, const TF* s, TF& c0, TF& c1, TF& c2)
+{
+    const TF t0 = s[0] * rx + s[3] * ry + s[4] * rz;
+    const TF t1 = s[3] * rx + s[1] * ry + s[5] * rz;
+    const TF t2 = s[4] * rx + s[5] * ry + s[2] * rz;
+    const TF rsr = rx * t0 + ry * t1 + rz * t2;
+    const TF g = al * rsr + be * (s[0] + s[1] + s[2]);
+    const TF be2 = be + be;
+    c0 += g * rx + be2 * t0;
+    c1 += g * ry + be2 * t1;
+    c2 += g * rz + be2 * t2;
+}
 
 // c = a1 f + b (r.f) r
 template <typename TF>
@@ -367,14 +443,20 @@ __global__ void k_zero_f64(double* __restrict__ p, int64_t count)
     if (i < count) p[i] = 0.0;
 }
 
-template <typename TF, bool Fast>
+// ST: stresslet sources too (srec: sorted symmetric tensors, 6 per particle); T^N is odd,
+// so the source side of a pair takes -T^N(r) S_target.
+template <typename TF, bool Fast, bool ST>
 __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__ rec,
+                                                const double* __restrict__ srec,
                                                 const int* __restrict__ start,
                                                 const int* __restrict__ chunk_off, Geometry g,
                                                 PairArgs a, double* __restrict__ u_near)
 {
+    constexpr int NS = ST ? 6 : 1;
     __shared__ double tgt[3][kWave];
     __shared__ TF tgtf[3][kWave];
+    __shared__ TF tgts[NS][kWave];
+    __shared__ TF rings[NS][kSymRing];
     __shared__ double acc[3][kWave];
     __shared__ double ring[3][kSymRing];
     __shared__ TF ringf[3][kSymRing];
@@ -416,6 +498,11 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
         acc[d][lane] = 0.0;
         racc[d][lane] = 0.0;
     }
+    if (ST) {
+        const int ii = active ? i : first;
+#pragma unroll
+        for (int c = 0; c < NS; ++c) tgts[c][lane] = (TF)srec[6 * (int64_t)ii + c];
+    }
     __syncthreads();
 
     int rhead = 0, rcount = 0;
@@ -446,9 +533,26 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
                 const double rz = tgt[2][tt] - ring[2][slot];
                 const double r2 = rx * rx + ry * ry + rz * rz;
                 TF a1, b, c0, c1, c2, d0, d1, d2;
-                Coef<TF, Fast>::eval(r2, a, a1, b);
-                apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, ringf[0][slot], ringf[1][slot], ringf[2][slot], c0, c1, c2);
-                apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, tgtf[0][tt], tgtf[1][tt], tgtf[2][tt], d0, d1, d2);
+                if (ST) {
+                    TF al, be;
+                    CoefSt<TF, Fast>::eval(r2, a, a1, b, al, be);
+                    apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, ringf[0][slot], ringf[1][slot], ringf[2][slot], c0, c1,
+                              c2);
+                    apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, tgtf[0][tt], tgtf[1][tt], tgtf[2][tt], d0, d1, d2);
+                    TF ss[6], st[6];
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) {
+                        ss[c] = rings[c % NS][slot];
+                        st[c] = -tgts[c % NS][tt];  // T^N(-r) = -T^N(r)
+                    }
+                    apply_st<TF>(al, be, (TF)rx, (TF)ry, (TF)rz, ss, c0, c1, c2);
+                    apply_st<TF>(al, be, (TF)rx, (TF)ry, (TF)rz, st, d0, d1, d2);
+                } else {
+                    Coef<TF, Fast>::eval(r2, a, a1, b);
+                    apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, ringf[0][slot], ringf[1][slot], ringf[2][slot], c0, c1,
+                              c2);
+                    apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, tgtf[0][tt], tgtf[1][tt], tgtf[2][tt], d0, d1, d2);
+                }
                 atomicAdd(&acc[0][tt], (double)c0);
                 atomicAdd(&acc[1][tt], (double)c1);
                 atomicAdd(&acc[2][tt], (double)c2);
@@ -531,6 +635,10 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
                             ringf[1][slot] = (TF)f1;
                             ringf[2][slot] = (TF)f2;
                             ringk[slot] = koff + s;
+                            if (ST) {
+#pragma unroll
+                                for (int c = 0; c < NS; ++c) rings[c][slot] = (TF)srec[6 * (int64_t)s + c];
+                            }
                         }
                         rcount += __popcll(bm);
                         __syncthreads();
@@ -559,7 +667,7 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
 
 }  // namespace
 
-hipError_t launch_p2p(const Plan& pl, const Work& w, int n, hipStream_t s)
+hipError_t launch_p2p(const Plan& pl, const Work& w, int n, hipStream_t s, bool st)
 {
     if (n <= 0) return hipSuccess;
     PairArgs a;
@@ -568,6 +676,8 @@ hipError_t launch_p2p(const Plan& pl, const Work& w, int n, hipStream_t s)
     a.rc2 = pl.rc * pl.rc;
     a.four_xi_over_sqrtpi = 4.0 * pl.xi / sqrt(M_PI);
     a.xi2_log2e = a.xi2 * 1.4426950408889634;
+    a.six_xi_over_sqrtpi = 6.0 * pl.xi / sqrt(M_PI);
+    a.four_xi3_over_sqrtpi = 4.0 * pl.xi * pl.xi * pl.xi / sqrt(M_PI);
     for (int k = 0; k <= kScreenDeg64; ++k) a.c64[k] = kScreenC64[k];
     for (int k = 0; k <= kScreenDeg64s; ++k) a.c64s[k] = kScreenC64s[k];
     for (int k = 0; k <= kScreenDeg32; ++k) a.c32[k] = (float)kScreenC32[k];
@@ -581,7 +691,7 @@ hipError_t launch_p2p(const Plan& pl, const Work& w, int n, hipStream_t s)
     const dim3 grid((unsigned)waves), block(kWave);
     const Rec64* rec = (const Rec64*)w.rec;
     const bool f64 = pl.mode == EWALD_FP64;
-    if (pl.deterministic) {
+    if (pl.deterministic && !st) {
         // FP32 bulk accumulates in FP64 as well: LDS atomic adds of FP64 are fast on
         // gfx950, those of FP32 are not (measured: 3x slower kernel)
         if (f64 && fast)
@@ -597,15 +707,28 @@ hipError_t launch_p2p(const Plan& pl, const Work& w, int n, hipStream_t s)
     }
     const int64_t cnt = 3 * (int64_t)n;
     hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, w.u_near, cnt);
+    const double* sr = w.srec;
+    if (st) {
+        if (f64 && fast)
+            hipLaunchKernelGGL((k_p2p_sym<double, true, true>), grid, block, 0, s, n, rec, sr, w.start, w.chunk_off,
+                               pl.g, a, w.u_near);
+        else if (f64)
+            hipLaunchKernelGGL((k_p2p_sym<double, false, true>), grid, block, 0, s, n, rec, sr, w.start,
+                               w.chunk_off, pl.g, a, w.u_near);
+        else
+            hipLaunchKernelGGL((k_p2p_sym<float, false, true>), grid, block, 0, s, n, rec, sr, w.start,
+                               w.chunk_off, pl.g, a, w.u_near);
+        return hipGetLastError();
+    }
     if (f64 && fast)
-        hipLaunchKernelGGL((k_p2p_sym<double, true>), grid, block, 0, s, n, rec, w.start, w.chunk_off, pl.g, a,
-                           w.u_near);
+        hipLaunchKernelGGL((k_p2p_sym<double, true, false>), grid, block, 0, s, n, rec, sr, w.start, w.chunk_off,
+                           pl.g, a, w.u_near);
     else if (f64)
-        hipLaunchKernelGGL((k_p2p_sym<double, false>), grid, block, 0, s, n, rec, w.start, w.chunk_off, pl.g, a,
-                           w.u_near);
+        hipLaunchKernelGGL((k_p2p_sym<double, false, false>), grid, block, 0, s, n, rec, sr, w.start,
+                           w.chunk_off, pl.g, a, w.u_near);
     else
-        hipLaunchKernelGGL((k_p2p_sym<float, false>), grid, block, 0, s, n, rec, w.start, w.chunk_off, pl.g, a,
-                           w.u_near);
+        hipLaunchKernelGGL((k_p2p_sym<float, false, false>), grid, block, 0, s, n, rec, sr, w.start,
+                           w.chunk_off, pl.g, a, w.u_near);
     return hipGetLastError();
 }
 

@@ -101,6 +101,25 @@ __global__ void k_gather64(int n, const double* __restrict__ x, const double* __
     rec[s] = r;
 }
 
+// Symmetric part of each stresslet source tensor q n^T, in sorted order: the stresslet
+// kernel is symmetric in all three indices, so only (q n^T + n q^T)/2 contributes.
+__global__ void k_gather_st(int n, const double* __restrict__ q, const double* __restrict__ nrm,
+                            const int* __restrict__ perm, double* __restrict__ srec)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int i = perm[s];
+    const double q0 = q[i], q1 = q[(int64_t)n + i], q2 = q[2 * (int64_t)n + i];
+    const double n0 = nrm[i], n1 = nrm[(int64_t)n + i], n2 = nrm[2 * (int64_t)n + i];
+    double* o = srec + 6 * (int64_t)s;
+    o[0] = q0 * n0;
+    o[1] = q1 * n1;
+    o[2] = q2 * n2;
+    o[3] = 0.5 * (q0 * n1 + q1 * n0);
+    o[4] = 0.5 * (q0 * n2 + q2 * n0);
+    o[5] = 0.5 * (q1 * n2 + q2 * n1);
+}
+
 // Number of 64-target waves per P2P tile.
 __global__ void k_tile_chunks(Geometry g, const int* __restrict__ start, int* __restrict__ chunks)
 {
@@ -240,6 +259,14 @@ hipError_t launch_sort(const Plan& pl, const Work& w, int n, const double* x, co
     hipLaunchKernelGGL(k_tile_chunks, dim3(blocks_for(g.ntiles, 256)), dim3(256), 0, s, g, w.start,
                        w.count);
     return launch_exclusive_scan(w.count, w.chunk_off, g.ntiles, w.part, s);
+}
+
+hipError_t launch_gather_st(const Plan& pl, const Work& w, int n, const double* q, const double* nrm,
+                            hipStream_t s)
+{
+    (void)pl;
+    hipLaunchKernelGGL(k_gather_st, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, q, nrm, w.perm, w.srec);
+    return hipGetLastError();
 }
 
 }  // namespace ewald

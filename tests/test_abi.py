@@ -128,3 +128,16 @@ def test_cost_model_grows_with_work():
     b = E.resolve((1, 1, 1), 1e-6, precision="fp32", n_max=10**6, grid=(128, 128, 128))
     c = E.resolve((1, 1, 1), 1e-8, precision="fp64", n_max=10**6, grid=(128, 128, 128))
     assert a["predicted_ms"] < b["predicted_ms"] < c["predicted_ms"]
+
+
+def test_stresslet_plans():
+    """EWALD_FLAG_STRESSLET sizes a larger workspace (sorted tensors, 9-component grid) and is
+    refused together with EWALD_FLAG_DETERMINISTIC."""
+    g = (32, 32, 32)
+    a = E.resolve((1, 1, 1), 1e-6, grid=g, n_max=1000)
+    b = E.resolve((1, 1, 1), 1e-6, grid=g, n_max=1000, stresslet=True)
+    assert b["stresslet"] and not a["stresslet"]
+    assert b["workspace_bytes"] >= a["workspace_bytes"] + 6 * 32**3 * 8 + 48 * 1000
+    with pytest.raises(E.EwaldError) as ei:
+        E.resolve((1, 1, 1), 1e-6, grid=g, n_max=1000, stresslet=True, deterministic=True)
+    assert ei.value.code == E.EWALD_EUNSUPPORTED
