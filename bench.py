@@ -259,8 +259,8 @@ def main():
     p2p_s = stages["p2p"] * 1e-3
     peak = FP64_VECTOR_TFLOPS if precision == "fp64" else FP32_VECTOR_TFLOPS
     achieved = (pairs * P2P_FLOPS_PER_PAIR / p2p_s / 1e12) if pairs else None
-    kernel = ("k_p2p_sym<double, %s>" % ("true" if wl.tol >= 1e-10 else "false")) if precision == "fp64" \
-        else "k_p2p_sym<float, false>"
+    kernel = ("k_p2p_sym<double, %s, false>" % ("true" if wl.tol >= 1e-10 else "false")) if precision == "fp64" \
+        else "k_p2p_sym<float, false, false>"
     roofline = {
         "kernel": kernel,
         "bound": "alu",
@@ -289,6 +289,26 @@ def main():
                              "rel_err_vs_gaussian_window_result": float(
                                  (torch.linalg.norm(u_kb - u) / torch.linalg.norm(u)).item())}
         del kbp, u_kb
+        # combined single and double layer sources (the paper's benchmark workload): the same
+        # particles with stresslet vectors q, n ~ N(0, 1) per component
+        rng = np.random.default_rng(wl.seed + 500)
+        qd = torch.from_numpy(rng.standard_normal((3, wl.n))).to(dev)
+        nd = torch.from_numpy(rng.standard_normal((3, wl.n))).to(dev)
+        stp = E.Plan(wl.box, wl.tol, grid=wl.grid, precision=precision, n_max=wl.n, timers=True, stresslet=True)
+        ws_st = stp.workspace(wl.n, dev)
+        u_st = torch.empty_like(x)
+        for _ in range(2):
+            stp.eval_combined(x, f, qd, nd, out=u_st, workspace=ws_st)
+        torch.cuda.synchronize()
+        st_ms = {k: 0.0 for k in E.STAGES}
+        for _ in range(5):
+            stp.eval_combined(x, f, qd, nd, out=u_st, workspace=ws_st)
+            torch.cuda.synchronize()
+            for k, v in stp.stage_ms().items():
+                st_ms[k] += v / 5
+        legs["combined_stresslet"] = {"grid": list(stp.info["grid"]), "P": stp.info["P"], "stage_ms": st_ms,
+                                      "particles_per_s": wl.n / (st_ms["total"] * 1e-3)}
+        del stp, ws_st, u_st, qd, nd
         log("extra plans:", json.dumps(legs))
     # P2G GB/s: algorithmic bytes = particle reads (6 reals) + one write of the 3-component grid
     real = 8 if precision == "fp64" else 4
