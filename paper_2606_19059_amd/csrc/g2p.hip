@@ -98,11 +98,207 @@ __global__ __launch_bounds__(64) void k_g2p(int n, const typename RecView<T>::Re
 }
 
 
+// LDS-tiled G2P.  A block of four wavefronts takes kTileTargets consecutive cell-sorted
+// targets (a compact group: sort order is tile-major with Morton columns inside a tile),
+// stages the union of their P^3 stencils into LDS one grid component at a time (one pass
+// over that region, coalesced along z, periodic wrap per element), and every target then
+// gathers its stencil from LDS: each grid value read from L2 serves all targets whose
+// stencils contain it, and the gathers run at LDS bandwidth.  A block whose region does not
+// fit the LDS budget gathers directly from the grid instead (same arithmetic and order of
+// summation within a target).  Weights: one lane per (target, axis, offset); partial sums
+// reduced per wave with shuffles; lane q of the block writes target q's result.
+constexpr int kTileTargets = 32;
+constexpr int kTileWaves = 4;
+
+template <typename T, typename TG, int P>
+__global__ __launch_bounds__(kTileWaves * 64) void k_g2p_tile(int n, const Rec64* __restrict__ rec,
+                                                             const TG* __restrict__ grid, Geometry g,
+                                                             WinArgs<T> wa, double self_coef,
+                                                             const double* __restrict__ u_near,
+                                                             const double* __restrict__ f_in, double* __restrict__ u,
+                                                             double* __restrict__ u_near_out,
+                                                             double* __restrict__ u_far_out, int max_points)
+{
+    extern __shared__ unsigned char smem_raw[];
+    TG* reg = reinterpret_cast<TG*>(smem_raw);
+    __shared__ T sw[kTileTargets][3][P];
+    __shared__ int anc[kTileTargets][3];
+    __shared__ double res[kTileTargets][3];
+    __shared__ int lo_s[3], hi_s[3];
+    constexpr int kPass = (P * P + kWave - 1) / kWave;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    const int s0 = xcd_remap((int)blockIdx.x, (int)gridDim.x) * kTileTargets;
+    const int cnt = min(kTileTargets, n - s0);
+    const int M1 = g.M[0], M2 = g.M[1], M3 = g.M[2];
+    const int64_t nc = g.ncells;
+    if (tid < 3) {
+        lo_s[tid] = 0x7fffffff;
+        hi_s[tid] = -0x7fffffff;
+    }
+    __syncthreads();
+    if (tid < cnt) {
+        const Rec64& r = rec[s0 + tid];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int a = r.c[d] - P / 2 + 1;  // stencil anchor (unwrapped)
+            anc[tid][d] = a;
+            atomicMin(&lo_s[d], a);
+            atomicMax(&hi_s[d], a);
+        }
+    }
+    for (int k = tid; k < cnt * 3 * P; k += kTileWaves * kWave) {
+        const int q = k / (3 * P), d = (k / P) % 3, j = k % P;
+        int c[3];
+        T t[3], f[3];
+        RecView<T>::load(rec[s0 + q], g, c, t, f);
+        const T td = (d == 0) ? t[0] : (d == 1 ? t[1] : t[2]);
+        sw[q][d][j] = window_weight_one<T, P>(j, td, wa);
+    }
+    __syncthreads();
+    const int E0 = hi_s[0] - lo_s[0] + P, E1 = hi_s[1] - lo_s[1] + P, E2 = hi_s[2] - lo_s[2] + P;
+    const int E12 = E1 * E2;
+    const int tot = E0 * E12;
+    if ((int64_t)3 * tot <= max_points) {
+        // the three components fit together: one staging pass, one gather per target
+        for (int idx = tid; idx < tot; idx += kTileWaves * kWave) {
+            const int ix = idx / E12, rem = idx - ix * E12;
+            const int iy = rem / E2, iz = rem - iy * E2;
+            const int64_t gi = ((int64_t)wrapi(lo_s[0] + ix, M1) * M2 + wrapi(lo_s[1] + iy, M2)) * M3 +
+                               wrapi(lo_s[2] + iz, M3);
+            reg[idx] = grid[gi];
+            reg[tot + idx] = grid[nc + gi];
+            reg[2 * tot + idx] = grid[2 * nc + gi];
+        }
+        __syncthreads();
+        for (int q = wid; q < cnt; q += kTileWaves) {
+            const int ox = anc[q][0] - lo_s[0], oy = anc[q][1] - lo_s[1], oz = anc[q][2] - lo_s[2];
+            T wx[P];
+#pragma unroll
+            for (int ix = 0; ix < P; ++ix) wx[ix] = sw[q][0][ix];
+            TG a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll
+            for (int pass = 0; pass < kPass; ++pass) {
+                const int yz = pass * kWave + lane;
+                if (yz < P * P) {
+                    const int jy = yz / P, kz = yz - jy * P;
+                    const T wyz = sw[q][1][jy] * sw[q][2][kz];
+                    const TG* rp = reg + ox * E12 + (oy + jy) * E2 + oz + kz;
+#pragma unroll
+                    for (int ix = 0; ix < P; ++ix) {
+                        const TG wv = wx[ix] * wyz;
+                        a0 += wv * rp[ix * E12];
+                        a1 += wv * rp[tot + ix * E12];
+                        a2 += wv * rp[2 * tot + ix * E12];
+                    }
+                }
+            }
+            const double b0 = wave_sum((double)a0), b1 = wave_sum((double)a1), b2 = wave_sum((double)a2);
+            if (lane == 0) {
+                res[q][0] = b0;
+                res[q][1] = b1;
+                res[q][2] = b2;
+            }
+        }
+        __syncthreads();
+    } else if (tot <= max_points) {
+        for (int comp = 0; comp < 3; ++comp) {
+            const TG* gc = grid + comp * nc;
+            for (int idx = tid; idx < tot; idx += kTileWaves * kWave) {
+                const int ix = idx / E12, rem = idx - ix * E12;
+                const int iy = rem / E2, iz = rem - iy * E2;
+                const int gx = wrapi(lo_s[0] + ix, M1), gy = wrapi(lo_s[1] + iy, M2), gz = wrapi(lo_s[2] + iz, M3);
+                reg[idx] = gc[((int64_t)gx * M2 + gy) * M3 + gz];
+            }
+            __syncthreads();
+            for (int q = wid; q < cnt; q += kTileWaves) {
+                const int ox = anc[q][0] - lo_s[0], oy = anc[q][1] - lo_s[1], oz = anc[q][2] - lo_s[2];
+                T wx[P];
+#pragma unroll
+                for (int ix = 0; ix < P; ++ix) wx[ix] = sw[q][0][ix];
+                TG acc = 0;
+#pragma unroll
+                for (int pass = 0; pass < kPass; ++pass) {
+                    const int yz = pass * kWave + lane;
+                    if (yz < P * P) {
+                        const int jy = yz / P, kz = yz - jy * P;
+                        const T wyz = sw[q][1][jy] * sw[q][2][kz];
+                        const TG* rp = reg + ox * E12 + (oy + jy) * E2 + oz + kz;
+#pragma unroll
+                        for (int ix = 0; ix < P; ++ix) acc += (TG)(wx[ix] * wyz) * rp[ix * E12];
+                    }
+                }
+                const double s = wave_sum((double)acc);
+                if (lane == 0) res[q][comp] = s;
+            }
+            __syncthreads();
+        }
+    } else {
+        for (int q = wid; q < cnt; q += kTileWaves) {
+            TG a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll
+            for (int pass = 0; pass < kPass; ++pass) {
+                const int yz = pass * kWave + lane;
+                if (yz < P * P) {
+                    const int jy = yz / P, kz = yz - jy * P;
+                    const T wyz = sw[q][1][jy] * sw[q][2][kz];
+                    const int64_t col = (int64_t)wrapi(anc[q][1] + jy, M2) * M3 + wrapi(anc[q][2] + kz, M3);
+                    for (int ix = 0; ix < P; ++ix) {
+                        const int64_t idx = (int64_t)wrapi(anc[q][0] + ix, M1) * M2 * M3 + col;
+                        const TG wv = sw[q][0][ix] * wyz;
+                        a0 += wv * grid[idx];
+                        a1 += wv * grid[nc + idx];
+                        a2 += wv * grid[2 * nc + idx];
+                    }
+                }
+            }
+            const double b0 = wave_sum((double)a0), b1 = wave_sum((double)a1), b2 = wave_sum((double)a2);
+            if (lane == 0) {
+                res[q][0] = b0;
+                res[q][1] = b1;
+                res[q][2] = b2;
+            }
+        }
+        __syncthreads();
+    }
+    if (tid < cnt) {
+        const int s = s0 + tid;
+        const int orig = rec[s].orig;
+        const int64_t nn = n;
+        const double n0 = u_near[s], n1 = u_near[nn + s], n2 = u_near[2 * nn + s];
+        if (u) {
+            u[orig] = n0 + res[tid][0] - self_coef * f_in[orig];
+            u[nn + orig] = n1 + res[tid][1] - self_coef * f_in[nn + orig];
+            u[2 * nn + orig] = n2 + res[tid][2] - self_coef * f_in[2 * nn + orig];
+        } else {
+            u_near_out[orig] = n0;
+            u_near_out[nn + orig] = n1;
+            u_near_out[2 * nn + orig] = n2;
+            u_far_out[orig] = res[tid][0];
+            u_far_out[nn + orig] = res[tid][1];
+            u_far_out[2 * nn + orig] = res[tid][2];
+        }
+    }
+}
+
 template <typename T, typename TG, int P>
 hipError_t launch_g2p_t(const Plan& pl, const Work& w, int n, const double* f, double* u, double* un,
                         double* uf, hipStream_t s)
 {
     const double self_coef = 4.0 * pl.xi / sqrt(M_PI);
+    // LDS-tiled kernel (region budget: what a workgroup may use beyond its static arrays, at
+    // most half of a CU's 160 KB so that two blocks share a CU) when a P^3 stencil fits; the
+    // one-wave-per-target kernel otherwise
+    const int static_bytes = (int)(sizeof(T) * kTileTargets * 3 * P + (sizeof(int) * 3 + sizeof(double) * 3) *
+                                   kTileTargets + 64);
+    const int budget = std::min(pl.lds_per_block, 80 * 1024) - static_bytes;
+    const int max_points = budget / (int)sizeof(TG);
+    if (max_points >= P * P * P) {
+        hipLaunchKernelGGL((k_g2p_tile<T, TG, P>), dim3((n + kTileTargets - 1) / kTileTargets),
+                           dim3(kTileWaves * kWave), (size_t)max_points * sizeof(TG), s, n, (const Rec64*)w.rec,
+                           (const TG*)w.grid, pl.g, make_win_args<T>(pl), self_coef, w.u_near, f, u, un, uf,
+                           max_points);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL((k_g2p<T, TG, P>), dim3((n + kG2PPerWave - 1) / kG2PPerWave), dim3(kWave), 0, s, n,
                        (const typename RecView<T>::Rec*)w.rec, (const TG*)w.grid, pl.g, make_win_args<T>(pl),
                        self_coef, w.u_near, f, u, un, uf);
