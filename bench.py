@@ -309,6 +309,22 @@ def main():
         legs["combined_stresslet"] = {"grid": list(stp.info["grid"]), "P": stp.info["P"], "stage_ms": st_ms,
                                       "particles_per_s": wl.n / (st_ms["total"] * 1e-3)}
         del stp, ws_st, u_st, qd, nd
+        # the 1e-6 headline: FP32 bulk against the plain FP64 path at equal accuracy, on the H
+        # particles (1e6 uniform, 128^3), errors against an FP64 evaluation at tol 1e-8
+        hw = W.WORKLOADS["H"]
+        hx, hf = hw.make()
+        hX, hF = torch.from_numpy(hx).to(dev), torch.from_numpy(hf).to(dev)
+        ref = E.Plan(hw.box, 1e-8, n_max=hw.n, precision="fp64").eval(hX, hF)
+        head = {}
+        for prec in ("fp32", "fp64"):
+            hp = E.Plan(hw.box, hw.tol, grid=hw.grid, precision=prec, n_max=hw.n, timers=True)
+            ms_h, u_h = timed_evals(hp, hX, hF, 5, 2)
+            head[prec] = {"grid": list(hp.info["grid"]), "P": hp.info["P"], "measured_ms": ms_h,
+                          "particles_per_s": hw.n / (ms_h * 1e-3),
+                          "rel_err_vs_fp64_1e-8": float((torch.linalg.norm(u_h - ref) / torch.linalg.norm(ref)).item())}
+            del hp, u_h
+        legs["H_1e-6_fp32_vs_fp64"] = head
+        del hX, hF, ref
         log("extra plans:", json.dumps(legs))
     # P2G GB/s: algorithmic bytes = particle reads (6 reals) + one write of the 3-component grid
     real = 8 if precision == "fp64" else 4

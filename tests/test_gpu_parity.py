@@ -332,3 +332,14 @@ def test_kb_meets_tolerance_with_smaller_support(tol):
     print("kb tol %g P %d (gaussian P %d) err %.3e" % (tol, pk.info["P"], pg.info["P"], err))
     assert err <= tol
     assert pk.info["P"] < pg.info["P"]
+
+
+def test_largest_grid():
+    """The largest grid the plan accepts (512^3, 3 x 134M FP32 points) end to end."""
+    E = _E()
+    x, f = W.particles(2000, (1, 1, 1), seed=23)
+    pl = E.Plan((1, 1, 1), 1e-4, grid=(512, 512, 512), n_max=2000, precision="fp32")
+    u = host(pl.eval(dev(x), dev(f)))
+    err = oracle.rel_err(u, oracle.ewald_sum(x, f, (1, 1, 1)))
+    print("512^3: P %d r_c %.4f err %.2e" % (pl.info["P"], pl.info["r_c"], err))
+    assert err <= 1e-4

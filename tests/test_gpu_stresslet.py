@@ -99,3 +99,19 @@ def test_combined_entry_point_errors():
     with pytest.raises(E.EwaldError) as ei:
         plain.eval_combined(dev(x), dev(f), dev(q), dev(nr))
     assert ei.value.code == E.EWALD_EINVAL
+
+
+def test_combined_empty_and_single_particle():
+    """n = 0 is a no-op; one particle's stresslet sees only its own periodic images."""
+    import paper_2606_19059_amd as E
+
+    box = (1.0, 1.0, 1.0)
+    pl = E.Plan(box, 1e-8, grid=(32, 32, 32), n_max=4, stresslet=True)
+    z = torch.empty((3, 0), dtype=torch.float64, device="cuda")
+    assert pl.eval_combined(z, z, z, z).shape == (3, 0)
+    x = np.array([[0.3], [0.6], [0.1]])
+    f = np.array([[0.2], [-0.4], [1.0]])
+    q = np.array([[1.0], [0.5], [-0.3]])
+    nr = np.array([[0.2], [-1.0], [0.4]])
+    u = host(pl.eval_combined(dev(x), dev(f), dev(q), dev(nr)))
+    assert oracle.rel_err(u, oracle.ewald_sum(x, f, box, q=q, nrm=nr)) < 1e-7
