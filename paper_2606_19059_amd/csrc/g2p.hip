@@ -56,7 +56,7 @@ __global__ __launch_bounds__(64) void k_g2p(int n, const typename RecView<T>::Re
             sw[d][j] = window_weight_one<T, P>(j, td, wa);
         }
         __syncthreads();
-        TG a0 = 0, a1 = 0, a2 = 0;
+        double a0 = 0, a1 = 0, a2 = 0;  // FP64 sums in every mode (see below)
 #pragma unroll
         for (int pass = 0; pass < kPass; ++pass) {
             const int yz = pass * kWave + lane;
@@ -69,10 +69,10 @@ __global__ __launch_bounds__(64) void k_g2p(int n, const typename RecView<T>::Re
                 for (int ix = 0; ix < P; ++ix) {
                     const int gx = wrapi(c[0] - P / 2 + 1 + ix, M1);
                     const int64_t idx = (int64_t)gx * M2 * M3 + col;
-                    const TG wv = sw[0][ix] * wyz;
-                    a0 += wv * grid[idx];
-                    a1 += wv * grid[nc + idx];
-                    a2 += wv * grid[2 * nc + idx];
+                    const double wv = (double)(sw[0][ix] * wyz);
+                    a0 += wv * (double)grid[idx];
+                    a1 += wv * (double)grid[nc + idx];
+                    a2 += wv * (double)grid[2 * nc + idx];
                 }
             }
         }
@@ -98,6 +98,11 @@ __global__ __launch_bounds__(64) void k_g2p(int n, const typename RecView<T>::Re
 }
 
 
+// All G2P sums accumulate in FP64 (FP32 bulk included: the same VALU rate without packed
+// math).  The far field at a particle contains its own screened self-interaction, about
+// (4 xi / sqrt(pi)) f, which the self term removes; at large xi (fine grids) and for sparse
+// particles that cancellation is large, and FP32 partial sums would set an error floor.
+//
 // LDS-tiled G2P.  A block of four wavefronts takes kTileTargets consecutive cell-sorted
 // targets (a compact group: sort order is tile-major with Morton columns inside a tile),
 // stages the union of their P^3 stencils into LDS one grid component at a time (one pass
@@ -175,7 +180,7 @@ __global__ __launch_bounds__(kTileWaves * 64) void k_g2p_tile(int n, const Rec64
             T wx[P];
 #pragma unroll
             for (int ix = 0; ix < P; ++ix) wx[ix] = sw[q][0][ix];
-            TG a0 = 0, a1 = 0, a2 = 0;
+            double a0 = 0, a1 = 0, a2 = 0;  // FP64 sums in every mode (see below)
 #pragma unroll
             for (int pass = 0; pass < kPass; ++pass) {
                 const int yz = pass * kWave + lane;
@@ -185,10 +190,10 @@ __global__ __launch_bounds__(kTileWaves * 64) void k_g2p_tile(int n, const Rec64
                     const TG* rp = reg + ox * E12 + (oy + jy) * E2 + oz + kz;
 #pragma unroll
                     for (int ix = 0; ix < P; ++ix) {
-                        const TG wv = wx[ix] * wyz;
-                        a0 += wv * rp[ix * E12];
-                        a1 += wv * rp[tot + ix * E12];
-                        a2 += wv * rp[2 * tot + ix * E12];
+                        const double wv = (double)(wx[ix] * wyz);
+                        a0 += wv * (double)rp[ix * E12];
+                        a1 += wv * (double)rp[tot + ix * E12];
+                        a2 += wv * (double)rp[2 * tot + ix * E12];
                     }
                 }
             }
@@ -215,7 +220,7 @@ __global__ __launch_bounds__(kTileWaves * 64) void k_g2p_tile(int n, const Rec64
                 T wx[P];
 #pragma unroll
                 for (int ix = 0; ix < P; ++ix) wx[ix] = sw[q][0][ix];
-                TG acc = 0;
+                double acc = 0;
 #pragma unroll
                 for (int pass = 0; pass < kPass; ++pass) {
                     const int yz = pass * kWave + lane;
@@ -224,7 +229,7 @@ __global__ __launch_bounds__(kTileWaves * 64) void k_g2p_tile(int n, const Rec64
                         const T wyz = sw[q][1][jy] * sw[q][2][kz];
                         const TG* rp = reg + ox * E12 + (oy + jy) * E2 + oz + kz;
 #pragma unroll
-                        for (int ix = 0; ix < P; ++ix) acc += (TG)(wx[ix] * wyz) * rp[ix * E12];
+                        for (int ix = 0; ix < P; ++ix) acc += (double)(wx[ix] * wyz) * (double)rp[ix * E12];
                     }
                 }
                 const double s = wave_sum((double)acc);
@@ -234,7 +239,7 @@ __global__ __launch_bounds__(kTileWaves * 64) void k_g2p_tile(int n, const Rec64
         }
     } else {
         for (int q = wid; q < cnt; q += kTileWaves) {
-            TG a0 = 0, a1 = 0, a2 = 0;
+            double a0 = 0, a1 = 0, a2 = 0;  // FP64 sums in every mode (see below)
 #pragma unroll
             for (int pass = 0; pass < kPass; ++pass) {
                 const int yz = pass * kWave + lane;
@@ -244,10 +249,10 @@ __global__ __launch_bounds__(kTileWaves * 64) void k_g2p_tile(int n, const Rec64
                     const int64_t col = (int64_t)wrapi(anc[q][1] + jy, M2) * M3 + wrapi(anc[q][2] + kz, M3);
                     for (int ix = 0; ix < P; ++ix) {
                         const int64_t idx = (int64_t)wrapi(anc[q][0] + ix, M1) * M2 * M3 + col;
-                        const TG wv = sw[q][0][ix] * wyz;
-                        a0 += wv * grid[idx];
-                        a1 += wv * grid[nc + idx];
-                        a2 += wv * grid[2 * nc + idx];
+                        const double wv = (double)(sw[q][0][ix] * wyz);
+                        a0 += wv * (double)grid[idx];
+                        a1 += wv * (double)grid[nc + idx];
+                        a2 += wv * (double)grid[2 * nc + idx];
                     }
                 }
             }
