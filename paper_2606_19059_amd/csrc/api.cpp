@@ -249,6 +249,20 @@ int choose_tile(const double box[3], const int M[3], double n)
     return B;
 }
 
+// The window error models give an error relative to the far field u^F.  At a particle u^F
+// holds its own screened self-interaction, about (4 xi / sqrt(pi)) f, which the self term
+// cancels; where that exceeds the typical |u| / |f| (few particles, fine grids, large xi),
+// the window error relative to |u| grows by the ratio.  For n random sources in volume V,
+// |u| / |f| ~ sqrt(8 pi n Lmin / V) (the periodic sum of 1/r kernels over random forces);
+// half of it is taken as a conservative scale.
+double window_budget_factor(double xi, double n, const double box[3])
+{
+    const double V = box[0] * box[1] * box[2];
+    const double Lmin = std::min(box[0], std::min(box[1], box[2]));
+    const double u_over_f = std::max(1.0, 2.5 * std::sqrt(std::max(n, 1.0) * Lmin / V));
+    return std::max(1.0, 4.0 * xi / std::sqrt(M_PI) / u_over_f);
+}
+
 // smallest window support meeting the window error budget (16 if none does)
 int choose_P(bool kb, double h, double xi, double budget)
 {
@@ -358,7 +372,7 @@ int validate_and_resolve(const ewald_params* in, Plan* pl)
             const double xi = xi_from_grid(hh, third);
             const double rc = rc_from_xi(xi, third);
             if (rc > Lmin || rc < hl || xi * rc > kScreenXmax) continue;
-            const int P = p.P > 0 ? p.P : choose_P(kb, hh, xi, third);
+            const int P = p.P > 0 ? p.P : choose_P(kb, hh, xi, third / window_budget_factor(xi, n, p.box));
             const double t = model_ms(mode, g64, n, p.box, M, P, rc, choose_tile(p.box, M, n), nullptr);
             if (t < best) {
                 best = t;
@@ -400,7 +414,7 @@ int validate_and_resolve(const ewald_params* in, Plan* pl)
     // window support and shape
     const bool kb = (p.precision & EWALD_FLAG_WINDOW_KB) != 0;
     if (kb && p.P > 0 && p.P < 6) return fail(EWALD_EINVAL, "P = %d: the Kaiser-Bessel window needs P >= 6", p.P);
-    if (!(p.P > 0)) p.P = choose_P(kb, h, p.xi, third);
+    if (!(p.P > 0)) p.P = choose_P(kb, h, p.xi, third / window_budget_factor(p.xi, (double)p.n_max, p.box));
     if (!(p.window_shape > 0)) p.window_shape = kb ? kb_beta_over_p(p.P, h, p.xi) : best_shape(p.P, h, p.xi);
 
     pl->p = p;
