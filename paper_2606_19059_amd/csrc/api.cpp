@@ -604,10 +604,9 @@ int check_eval_args(ewald_plan_t plan, int64_t n, const void* x, const void* f, 
 enum class Out { Full, Parts, Spread, FarGrid };
 
 int run(ewald_plan_t plan, int64_t n64, const double* x, const double* f, void* o1, void* o2, void* ws,
-        int64_t wsb, void* stream, Out what, const double* q = nullptr, const double* nrm = nullptr)
+        int64_t wsb, void* stream, Out what, bool st = false, const double* q = nullptr, const double* nrm = nullptr)
 {
     Work w;
-    const bool st = q != nullptr || nrm != nullptr;
     if (st) {
         if (!plan) return fail(EWALD_EINVAL, "null plan");
         if (!reinterpret_cast<const Plan*>(plan)->stresslet)
@@ -742,16 +741,14 @@ int ewald_eval_parts(ewald_plan_t plan, int64_t n, const double* x, const double
 int ewald_eval_combined(ewald_plan_t plan, int64_t n, const double* x, const double* f, const double* q,
                         const double* nrm, double* u, void* workspace, int64_t workspace_bytes, void* stream)
 {
-    if (!q && !nrm) return fail(EWALD_EINVAL, "null stresslet vector pointer");
-    return run(plan, n, x, f, u, u, workspace, workspace_bytes, stream, Out::Full, q, nrm);
+    return run(plan, n, x, f, u, u, workspace, workspace_bytes, stream, Out::Full, true, q, nrm);
 }
 
 int ewald_eval_combined_parts(ewald_plan_t plan, int64_t n, const double* x, const double* f, const double* q,
                               const double* nrm, double* u_near, double* u_far, void* workspace,
                               int64_t workspace_bytes, void* stream)
 {
-    if (!q && !nrm) return fail(EWALD_EINVAL, "null stresslet vector pointer");
-    return run(plan, n, x, f, u_near, u_far, workspace, workspace_bytes, stream, Out::Parts, q, nrm);
+    return run(plan, n, x, f, u_near, u_far, workspace, workspace_bytes, stream, Out::Parts, true, q, nrm);
 }
 
 int ewald_spread(ewald_plan_t plan, int64_t n, const double* x, const double* f, void* grid, void* workspace,
