@@ -285,6 +285,7 @@ def main():
         kbp = E.Plan(wl.box, wl.tol, grid=wl.grid, precision=precision, n_max=wl.n, timers=True, window="kb")
         ms_kb, u_kb = timed_evals(kbp, x, f, 5, 2)
         legs["kb_window"] = {"grid": list(kbp.info["grid"]), "P": kbp.info["P"], "measured_ms": ms_kb,
+                             "stage_ms": kbp.stage_ms(),
                              "particles_per_s": wl.n / (ms_kb * 1e-3),
                              "rel_err_vs_gaussian_window_result": float(
                                  (torch.linalg.norm(u_kb - u) / torch.linalg.norm(u)).item())}
