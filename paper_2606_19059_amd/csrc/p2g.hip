@@ -43,6 +43,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_p2g_sweep(const typename RecVie
     __shared__ int run_pre[kMaxRuns + 1];
     __shared__ T sw[kChunk][3][P];
     __shared__ T sf[kChunk][3];
+    __shared__ T st[kChunk][3];  // in-cell fractions (Kaiser-Bessel weights are computed from them)
     __shared__ int soff[kChunk];
     __shared__ T red[kWaves - 1][3][64];
 
@@ -124,13 +125,28 @@ __global__ __launch_bounds__(kWaves * 64) void k_p2g_sweep(const typename RecVie
                 const int oz = czu - P / 2 + 1 - z0;
                 const int q = q0 + lane;
                 soff[q] = (oy + P) | ((oz + P) << 8);
-                T wv[P];
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    window_weights<T, P>(t[d], wa, wv);
-#pragma unroll
-                    for (int k = 0; k < P; ++k) sw[q][d][k] = wv[k];
                     sf[q][d] = f[d];
+                    st[q][d] = t[d];
+                }
+                if (!wa.kb) {
+                    // Gaussian: two exponentials and P products per axis on the staging lane
+                    T wv[P];
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        window_weights<T, P>(t[d], wa, wv);
+#pragma unroll
+                        for (int k = 0; k < P; ++k) sw[q][d][k] = wv[k];
+                    }
+                }
+            }
+            if (wa.kb) {
+                // Kaiser-Bessel: one polynomial per weight, spread over all lanes of the wave
+                __syncthreads();
+                for (int k = lane; k < cnt * 3 * P; k += kWave) {
+                    const int qq = q0 + k / (3 * P), d = (k / P) % 3, j = k % P;
+                    sw[qq][d][j] = window_weight_one<T, P>(j, st[qq][d], wa);
                 }
             }
             __syncthreads();
