@@ -291,13 +291,16 @@ hipError_t launch_g2p_t(const Plan& pl, const Work& w, int n, const double* f, d
 {
     const double self_coef = 4.0 * pl.xi / sqrt(M_PI);
     // LDS-tiled kernel (region budget: what a workgroup may use beyond its static arrays, at
-    // most half of a CU's 160 KB so that two blocks share a CU) when a P^3 stencil fits; the
-    // one-wave-per-target kernel otherwise
+    // most half of a CU's 160 KB so that two blocks share a CU) for grids above half of the
+    // 256 MB Infinity Cache, where the direct gathers of neighbouring targets stop hitting the
+    // on-chip caches (measured: c4's 201 MB grid 28.9 -> 19.8 ms); below that the
+    // one-wave-per-target kernel's cache hits beat the staging (a 25 MB FP32 grid: 2.6 vs 2.9 ms)
     const int static_bytes = (int)(sizeof(T) * kTileTargets * 3 * P + (sizeof(int) * 3 + sizeof(double) * 3) *
                                    kTileTargets + 64);
     const int budget = std::min(pl.lds_per_block, 80 * 1024) - static_bytes;
     const int max_points = budget / (int)sizeof(TG);
-    if (max_points >= P * P * P) {
+    const double grid_bytes = 3.0 * (double)pl.g.ncells * (double)sizeof(TG);
+    if (max_points >= P * P * P && grid_bytes > 128.0 * (1 << 20)) {
         hipLaunchKernelGGL((k_g2p_tile<T, TG, P>), dim3((n + kTileTargets - 1) / kTileTargets),
                            dim3(kTileWaves * kWave), (size_t)max_points * sizeof(TG), s, n, (const Rec64*)w.rec,
                            (const TG*)w.grid, pl.g, make_win_args<T>(pl), self_coef, w.u_near, f, u, un, uf,
