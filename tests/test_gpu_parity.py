@@ -343,3 +343,24 @@ def test_largest_grid():
     err = oracle.rel_err(u, oracle.ewald_sum(x, f, (1, 1, 1)))
     print("512^3: P %d r_c %.4f err %.2e" % (pl.info["P"], pl.info["r_c"], err))
     assert err <= 1e-4
+
+
+def test_tiled_g2p_on_a_large_grid():
+    """Grids above 128 MB use the LDS-tiled G2P; its three paths (components staged together,
+    one at a time, direct gathers) against the spectral oracle's far field.  Particles: a tight
+    cluster, a looser one and a uniform sprinkle, so the 32-target groups span small, medium
+    and large regions."""
+    E = _E()
+    box, grid, xi, P = (1.0, 1.0, 1.0), (256, 256, 256), 60.0, 8
+    rng = np.random.default_rng(31)
+    x = np.concatenate([0.3 + 0.01 * rng.random((3, 1500)), 0.6 + 0.05 * rng.random((3, 1000)),
+                        rng.random((3, 500))], axis=1)
+    f = rng.standard_normal((3, x.shape[1]))
+    m = 0.94 * math.sqrt(math.pi * P)
+    ref = S.far_field(x, f, box, grid, xi, P, m)
+    for prec, tol, bound in (("fp64", 1e-11, 1e-11), ("fp32", 1e-7, 1e-6), ("fp32", 1e-5, 3e-5)):
+        pl = E.Plan(box, tol, xi=xi, r_c=0.1, grid=grid, P=P, window_shape=m, n_max=x.shape[1], precision=prec)
+        _, uf = pl.eval_parts(dev(x), dev(f))
+        err = maxrel(host(uf), ref)
+        print("256^3 %s tol %g (FP64 grid: %s): far-field max rel err %.2e" % (prec, tol, pl.info["fourier_fp64"], err))
+        assert err < bound
