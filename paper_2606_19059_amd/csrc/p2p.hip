@@ -431,8 +431,10 @@ __global__ __launch_bounds__(64) void k_p2p(int n, const Rec64* __restrict__ rec
 // (the one-sided kernel above is the reproducible variant).
 //
 // Candidates are tested in diagonal order (lane t tests ring source (t + j) mod 16 at
-// step j), so that the queued pairs of one drain round have distinct targets and at most
-// four lanes per source: few conflicts in the LDS atomics of either side.
+// step j), so that the queued pairs of one drain round have distinct targets; the four
+// targets t, t + 16, t + 32, t + 48 that share a source add into separate copies of the
+// batch's source accumulators (summed when the batch retires), so neither side's LDS
+// atomics hit one address twice in a round.
 constexpr int kSymRing = 64;
 constexpr int kSymTest = 16;
 constexpr int kFar = 1 << 30;  // ring key offset of sources outside the targets' own tile
@@ -461,7 +463,7 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
     __shared__ double ring[3][kSymRing];
     __shared__ TF ringf[3][kSymRing];
     __shared__ int ringk[kSymRing];
-    __shared__ double racc[3][kSymRing];
+    __shared__ double racc[4][3][kSymTest];  // per quarter of the targets, per batch source
     __shared__ unsigned short queue[kSymTest * kWave];
     static_assert(kSymRing == kWave, "one ring slot per lane");
 
@@ -496,7 +498,7 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
         tgt[d][lane] = tx[d];
         tgtf[d][lane] = (TF)me.f[d];
         acc[d][lane] = 0.0;
-        racc[d][lane] = 0.0;
+        racc[lane >> 4][d][lane & 15] = 0.0;
     }
     if (ST) {
         const int ii = active ? i : first;
@@ -556,24 +558,31 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
                 atomicAdd(&acc[0][tt], (double)c0);
                 atomicAdd(&acc[1][tt], (double)c1);
                 atomicAdd(&acc[2][tt], (double)c2);
-                atomicAdd(&racc[0][slot], (double)d0);
-                atomicAdd(&racc[1][slot], (double)d1);
-                atomicAdd(&racc[2][slot], (double)d2);
+                const int rq = tt >> 4, sq = e >> 6;
+                atomicAdd(&racc[rq][0][sq], (double)d0);
+                atomicAdd(&racc[rq][1][sq], (double)d1);
+                atomicAdd(&racc[rq][2][sq], (double)d2);
             }
         }
         __syncthreads();
         // retire the cnt ring sources: their source-side sums go to u^N
         if (lane < cnt) {
             const int slot = (rhead + lane) & (kSymRing - 1);
-            const double v0 = racc[0][slot], v1 = racc[1][slot], v2 = racc[2][slot];
+            double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+#pragma unroll
+            for (int rq = 0; rq < 4; ++rq) {
+                v0 += racc[rq][0][lane];
+                v1 += racc[rq][1][lane];
+                v2 += racc[rq][2][lane];
+                racc[rq][0][lane] = 0.0;
+                racc[rq][1][lane] = 0.0;
+                racc[rq][2][lane] = 0.0;
+            }
             if (v0 != 0.0 || v1 != 0.0 || v2 != 0.0) {
                 const int64_t jj = ringk[slot] & (kFar - 1);
                 unsafeAtomicAdd(&u_near[jj], v0);
                 unsafeAtomicAdd(&u_near[(int64_t)n + jj], v1);
                 unsafeAtomicAdd(&u_near[2 * (int64_t)n + jj], v2);
-                racc[0][slot] = 0.0;
-                racc[1][slot] = 0.0;
-                racc[2][slot] = 0.0;
             }
         }
         __syncthreads();
