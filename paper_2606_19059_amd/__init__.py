@@ -215,6 +215,7 @@ class Plan:
         lib = load()
         p = make_params(box, tol, xi, r_c, grid, P, precision, n_max, window_shape, p2p_fp64_acc, timers,
                         window, deterministic, stresslet)
+        self._lib = lib  # kept so that the plan can be freed during interpreter shutdown
         h = ctypes.c_void_p()
         _check(lib.ewald_plan_create(ctypes.byref(p), ctypes.byref(h)))
         self._h = h
@@ -229,7 +230,7 @@ class Plan:
 
     def close(self):
         if getattr(self, "_h", None):
-            load().ewald_plan_destroy(self._h)
+            self._lib.ewald_plan_destroy(self._h)
             self._h = None
 
     @property
