@@ -58,10 +58,15 @@ enum {
                             self terms, final sum in FP64.  Below tol 1e-6 the grid and its
                             transforms are kept in FP64 (the FP32 round trip through the
                             3D FFT alone leaves ~2e-7 relative error); P2P and the window
-                            weights of G2P stay FP32 */
-    EWALD_FLAG_P2P_FP64_ACC = 1 << 8, /* FP32 bulk: accumulate each particle's near-field
-                                         sum in FP64 (automatic when tol < 1e-7) */
-    EWALD_FLAG_STAGE_TIMERS = 1 << 9, /* record per-stage HIP events (see ewald_stage_ms) */
+                            weights of G2P stay FP32.  All sums over pairs and stencils
+                            accumulate in FP64 */
+    EWALD_FLAG_P2P_FP64_ACC = 1 << 8, /* accepted for compatibility: the near-field sums are
+                                         always accumulated in FP64 (in FP32 bulk too: FP64
+                                         LDS atomics are fast on gfx950, FP32 ones are not) */
+    EWALD_FLAG_STAGE_TIMERS = 1 << 9, /* record per-stage HIP events (see ewald_stage_ms); the
+                                         events belong to the plan, so overlapping evaluations
+                                         of one timed plan on several streams time nothing
+                                         meaningful: time one evaluation at a time */
     EWALD_FLAG_WINDOW_KB = 1 << 10,   /* truncated Kaiser-Bessel window (Sec. 2.2) instead of the
                                          Gaussian: w0(d) = I0(beta sqrt(1 - (2d/(P h))^2)) / I0(beta) */
     EWALD_FLAG_DETERMINISTIC = 1 << 11, /* bitwise reproducible results: P2P evaluates every pair
