@@ -120,33 +120,53 @@ def timed_evals(plan, x, f, steps, warmup):
 def serving_leg(n_requests):
     """Stream of independent suspensions (N log-uniform in [1e3, 1e6], cubic or 1x1x2 box,
     uniform or blobs, tol in {1e-4, 1e-6, 1e-8}): saturated throughput with every request
-    waiting at t = 0, then Poisson arrivals at 0.8 of that rate for p50/p99 latency."""
+    waiting at t = 0, then Poisson arrivals at 0.5, 0.8 and 0.95 of that rate for p50/p99
+    latency, and once more at 0.8 under a forced 8 GiB HBM budget (admission waits)."""
     import torch
 
     from paper_2606_19059_amd import serve
     from paper_2606_19059_amd import workloads as W
 
-    reqs = W.serving_stream(n_requests, rate_per_s=0.0, seed=5)
-    jobs = serve.make_jobs(reqs)
+    jobs = serve.make_jobs(W.serving_stream(n_requests, rate_per_s=0.0, seed=5))
+
+    def reset(arrivals):
+        for j, a in zip(jobs, arrivals):
+            j.arrival = float(a)
+            j.admitted = j.done = float("nan")
+            j.u = None
+            j.slot = -1
+
+    def poisson(rate, seed):
+        return np.cumsum(np.random.default_rng(seed).exponential(1.0 / rate, len(jobs)))
+
     srv = serve.Server(n_slots=4)
     srv.run(jobs[: min(4, len(jobs))])  # plans, tables and workspaces become resident
     torch.cuda.synchronize()
-    for j in jobs:
-        j.arrival = 0.0
+    reset(np.zeros(len(jobs)))
     sat = serve.summarize(srv.run(jobs))
-    rate = 0.8 * sat["requests"] / sat["wall_s"]
-    reqs = W.serving_stream(n_requests, rate_per_s=rate, seed=5)
-    jobs2 = serve.make_jobs(reqs)
-    load = serve.summarize(srv.run(jobs2))
+    rate = sat["requests"] / sat["wall_s"]
+    loads = {}
+    for k, frac in enumerate((0.5, 0.8, 0.95)):
+        reset(poisson(frac * rate, 50 + k))
+        r = serve.summarize(srv.run(jobs))
+        loads["%.2f" % frac] = {"p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"], "particles_per_s": r["particles_per_s"]}
+    small = serve.Server(n_slots=4, hbm_budget=8 << 30)
+    reset(poisson(0.8 * rate, 60))
+    r = serve.summarize(small.run(jobs))
+    budget = {"budget_bytes": 8 << 30, "offered_load": 0.8, "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"],
+              "particles_per_s": r["particles_per_s"], "max_in_flight_bytes": small.max_in_flight_bytes,
+              "admissions_waiting_for_memory": small.memory_waits}
     return {
         "workload": "c5: %d requests, N log-uniform [1e3, 1e6], boxes 1^3 or 1x1x2, uniform or blobs, "
                     "tol in {1e-4, 1e-6, 1e-8} (FP32 bulk for tol >= 1e-6, FP64 below), 4 streams, "
                     "admission by HBM footprint" % n_requests,
         "saturated_particles_per_s": sat["particles_per_s"],
         "offered_load": 0.8,
-        "p50_ms": load["p50_ms"],
-        "p99_ms": load["p99_ms"],
-        "particles_per_s": load["particles_per_s"],
+        "p50_ms": loads["0.80"]["p50_ms"],
+        "p99_ms": loads["0.80"]["p99_ms"],
+        "particles_per_s": loads["0.80"]["particles_per_s"],
+        "by_offered_load": loads,
+        "hbm_budget_8GiB": budget,
     }
 
 
@@ -163,7 +183,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra-plans", action="store_true",
                     help="skip the cost-model plan and Kaiser-Bessel legs")
-    ap.add_argument("--serve-requests", type=int, default=40,
+    ap.add_argument("--serve-requests", type=int, default=200,
                     help="requests in the serving leg (Poisson stream of independent suspensions; 0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (reference for HBM byte counters)")

@@ -29,7 +29,7 @@ def _solo(job):
 def test_results_equal_alone_and_in_the_mix():
     from paper_2606_19059_amd import serve
 
-    jobs = _stream(14, seed=5)
+    jobs = _stream(30, seed=5)
     srv = serve.Server(n_slots=4)
     done = srv.run(jobs)
     torch.cuda.synchronize()
