@@ -117,10 +117,19 @@ __device__ inline double exp_neg_fast(double y, const PairArgs& a)
 }
 
 // Coefficients of G^N(r) f = a1 f + b (r.f) r for 0 < r^2 < r_c^2 (FP64)
+// 1/sqrt(r2) for finite r2 > 0: hardware estimate, then one third-order correction
+// y (1 + e/2 + 3e^2/8), e = 1 - r2 y^2 (no special-value handling)
+__device__ inline double rsqrt_pos(double r2)
+{
+    const double y = __builtin_amdgcn_rsq(r2);
+    const double e = fma(-r2 * y, y, 1.0);
+    return fma(y * e, fma(0.375, e, 0.5), y);
+}
+
 template <bool Fast>
 __device__ inline void coef64(double r2, const PairArgs& a, double& a1, double& b)
 {
-    const double rinv = rsqrt(r2);
+    const double rinv = rsqrt_pos(r2);
     const double x = a.xi * r2 * rinv;
     const double e = Fast ? exp_neg_fast(a.xi2 * r2, a) : exp(-a.xi2 * r2);
     const double C = e * screen_q64<Fast>(x, a);
@@ -298,7 +307,7 @@ __global__ __launch_bounds__(64) void k_p2p(int n, const Rec64* __restrict__ rec
     const Rec64 me = rec[active ? i : first];
 
     const int tc[3] = {t / (g.NT[1] * g.NT[2]), (t / g.NT[2]) % g.NT[1], t % g.NT[2]};
-    double w[3], blo[3], bhi[3], tx[3];
+    double w[3], blo[3], bhi[3], tx[3], oacc[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         w[d] = g.B * g.h[d];
@@ -424,20 +433,41 @@ __global__ __launch_bounds__(64) void k_p2p(int n, const Rec64* __restrict__ rec
 // G^N(r) f_i (to u_j).  Every unordered pair is visited once: a wave walks only the upper
 // half of the neighbour-tile offsets D (lexicographically D > 0), plus its own tile (D = 0)
 // restricted to sources with a larger sorted index than the target; the mirrored offset
-// -D carries the same pairs.  The target side accumulates in LDS as before; the source
-// side accumulates per ring slot in LDS and is added to u^N with one FP64 atomic per
-// component and source when the slot retires.  u^N is zeroed first.  The order of those
-// atomic additions varies between runs, so results agree to rounding, not bitwise
-// (the one-sided kernel above is the reproducible variant).
+// -D carries the same pairs.  The source side accumulates per ring entry in LDS and is
+// added to u^N with one FP64 atomic per component and source when the entry retires.
+// u^N is zeroed first.  The order of those atomic additions varies between runs, so
+// results agree to rounding, not bitwise (the one-sided kernel above is the reproducible
+// variant).
 //
-// Candidates are tested in diagonal order (lane t tests ring source (t + j) mod 16 at
-// step j), so that the queued pairs of one drain round have distinct targets; the four
-// targets t, t + 16, t + 32, t + 48 that share a source add into separate copies of the
-// batch's source accumulators (summed when the batch retires), so neither side's LDS
-// atomics hit one address twice in a round.
+// Stokeslet-only form (balanced drain).  LDS traffic, not arithmetic, bounds the queue
+// drain above (six LDS atomics and twelve operand loads per pair), so the target side is
+// kept in registers where possible.  Per batch of 32 ring entries each lane tests its own
+// target against all of them (a 32-bit mask; all lanes read the same entry, an LDS
+// broadcast).  With Q accepted pairs the batch takes R = ceil(Q / 64) rounds of one pair
+// per lane; a lane keeps up to R pairs of its own target (summed in registers) and puts
+// the rest in a queue, from which lanes with fewer than R pairs take work in their spare
+// rounds (target side by LDS atomics, about 15% of the pairs at uniform density).  Lanes
+// take their own sources in an order rotated by lane mod 32, so that the 32 lanes sharing
+// one copy of the batch's source accumulators meet different sources in a round.
+//
+// Stresslet form (queue drain): candidates are tested in diagonal order (lane t tests
+// ring source (t + j) mod 16 at step j), so that the queued pairs of one drain round have
+// distinct targets; the four targets t, t + 16, t + 32, t + 48 that share a source add
+// into separate copies of the batch's source accumulators (summed when the batch
+// retires), so neither side's LDS atomics hit one address twice in a round.
 constexpr int kSymRing = 64;
 constexpr int kSymTest = 16;
 constexpr int kFar = 1 << 30;  // ring key offset of sources outside the targets' own tile
+// Balanced (Stokeslet-only) form: batches of 32 ring entries, source accumulators in two
+// copies (lanes 0-31 and 32-63).  Queue bound: with c_t <= 32 pairs per lane, Q = sum c_t
+// and R = ceil(Q / 64) rounds, the excess sum over c_t >= R of (c_t - R) is at most
+// Q (32 - R) / 32 <= 2 R (32 - R) <= 512.
+constexpr int kBalBatch = 32;
+constexpr int kBalExcess = 512;
+static_assert(kBalBatch == 32 && kSymRing == 64, "the mask, ring and queue sizes assume 32-entry batches");
+
+// wave ballot of a condition, without materialising it as an integer first
+__device__ inline unsigned long long ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 __global__ void k_zero_f64(double* __restrict__ p, int64_t count)
 {
@@ -463,8 +493,11 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
     __shared__ double ring[3][kSymRing];
     __shared__ TF ringf[3][kSymRing];
     __shared__ int ringk[kSymRing];
-    __shared__ double racc[4][3][kSymTest];  // per quarter of the targets, per batch source
-    __shared__ unsigned short queue[kSymTest * kWave];
+    // batch size and copies of the per-batch source accumulators (per component, copy, entry)
+    constexpr int kB = ST ? kSymTest : kBalBatch;
+    constexpr int kCp = ST ? 4 : 2;
+    __shared__ double racc[3][kCp][kB];
+    __shared__ unsigned short queue[ST ? kSymTest * kWave : kBalExcess];
     static_assert(kSymRing == kWave, "one ring slot per lane");
 
     // plain block order: an XCD-aware order (each XCD sweeping a contiguous range) was
@@ -488,7 +521,7 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
     const Rec64 me = rec[active ? i : first];
 
     const int tc[3] = {t / (g.NT[1] * g.NT[2]), (t / g.NT[2]) % g.NT[1], t % g.NT[2]};
-    double w[3], blo[3], bhi[3], tx[3];
+    double w[3], blo[3], bhi[3], tx[3], oacc[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         w[d] = g.B * g.h[d];
@@ -498,7 +531,8 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
         tgt[d][lane] = tx[d];
         tgtf[d][lane] = (TF)me.f[d];
         acc[d][lane] = 0.0;
-        racc[lane >> 4][d][lane & 15] = 0.0;
+        racc[d][lane / kB][lane % kB] = 0.0;
+        oacc[d] = 0.0;
     }
     if (ST) {
         const int ii = active ? i : first;
@@ -510,6 +544,103 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
     int rhead = 0, rcount = 0;
 
     auto process = [&](int cnt) {
+      if constexpr (!ST) {
+        // 1. test: bit j of m is set when this lane's target pairs with batch entry j (all
+        //    lanes read the same entry: LDS broadcast)
+        //    Sources of other tiles are never at r = 0 and always follow the wave's own
+        //    tile in the ring, so a batch whose first entry is not of the own tile needs
+        //    only the cutoff test.
+        unsigned m = 0;
+        int qn = 0;
+        const bool own_tile = uniform_i(ringk[rhead]) < kFar;
+        if (own_tile) {
+            for (int j = 0; j < cnt; ++j) {
+                const int slot = (rhead + j) & (kSymRing - 1);
+                const double rx = tx[0] - ring[0][slot], ry = tx[1] - ring[1][slot], rz = tx[2] - ring[2][slot];
+                const double r2 = rx * rx + ry * ry + rz * rz;
+                const bool pass = (r2 < a.rc2) & (r2 > 0.0) & (ringk[slot] > i);
+                m = pass ? (m | (1u << j)) : m;
+                qn += __popcll(ballot(pass));
+            }
+        } else {
+            for (int j = 0; j < cnt; ++j) {
+                const int slot = (rhead + j) & (kSymRing - 1);
+                const double rx = tx[0] - ring[0][slot], ry = tx[1] - ring[1][slot], rz = tx[2] - ring[2][slot];
+                const bool pass = rx * rx + ry * ry + rz * rz < a.rc2;
+                m = pass ? (m | (1u << j)) : m;
+                qn += __popcll(ballot(pass));
+            }
+        }
+        const int rounds = (qn + kWave - 1) / kWave;
+        // 2. a lane keeps up to `rounds` of its target's pairs (taken in an order rotated by
+        //    lane mod 32, so that the lanes sharing a copy of the source accumulators meet
+        //    different sources in a round); the excess goes to the queue, for lanes that run
+        //    out of pairs of their own
+        const int rot = lane & (kB - 1);
+        const unsigned rm0 = rot ? ((m >> rot) | (m << (kB - rot))) : m;
+        unsigned rm = rm0;
+        const int c = __popc(m);
+        const int own_n = c < rounds ? c : rounds;
+        int ex = c - own_n;
+        int qx = 0;
+        for (;;) {
+            const bool wr = ex > 0;
+            const unsigned long long bw = ballot(wr);
+            if (bw == 0) break;
+            if (wr) {
+                const int p = 31 - __clz(rm);
+                rm ^= 1u << p;
+                queue[qx + lanes_below(bw)] = (unsigned short)(lane | (((p + rot) & (kB - 1)) << 6));
+                --ex;
+            }
+            qx += __popcll(bw);
+        }
+        __syncthreads();
+        // 3. `rounds` rounds, one pair per lane: the lane's own target while it has pairs
+        //    (target side summed in registers), then queue entries in order (target side by
+        //    LDS atomics); the source side goes to this lane quarter's copy of the batch
+        //    accumulators
+        int qb = 0;
+        for (int r = 0; r < rounds; ++r) {
+            // branch-free round: every lane reads a queue entry (in range, used only by
+            // donated lanes) and its target's data from LDS (its own target for own lanes)
+            const bool own = r < own_n;
+            const unsigned long long bi = ballot(!own);
+            const int q = qb + lanes_below(bi);
+            qb += __popcll(bi);
+            const bool don = !own && q < qx;
+            const int e = queue[q < qx ? q : 0];
+            const int pb = __ffs(rm) - 1;
+            rm = own ? (rm & (rm - 1)) : rm;
+            const int tt = own ? lane : (e & (kWave - 1));
+            const int sl = own ? ((pb + rot) & (kB - 1)) : ((e >> 6) & (kB - 1));
+            const int slot = (rhead + sl) & (kSymRing - 1);
+            const double rx = tgt[0][tt] - ring[0][slot];
+            const double ry = tgt[1][tt] - ring[1][slot];
+            const double rz = tgt[2][tt] - ring[2][slot];
+            const double r2 = rx * rx + ry * ry + rz * rz;
+            TF a1, b, c0, c1, c2, d0, d1, d2;
+            Coef<TF, Fast>::eval(r2, a, a1, b);
+            apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, ringf[0][slot], ringf[1][slot], ringf[2][slot], c0, c1, c2);
+            apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, tgtf[0][tt], tgtf[1][tt], tgtf[2][tt], d0, d1, d2);
+            if (own) {
+                oacc[0] += (double)c0;
+                oacc[1] += (double)c1;
+                oacc[2] += (double)c2;
+            }
+            if (don) {
+                atomicAdd(&acc[0][tt], (double)c0);
+                atomicAdd(&acc[1][tt], (double)c1);
+                atomicAdd(&acc[2][tt], (double)c2);
+            }
+            if (own || don) {
+                const int rq = lane / kB;
+                atomicAdd(&racc[0][rq][sl], (double)d0);
+                atomicAdd(&racc[1][rq][sl], (double)d1);
+                atomicAdd(&racc[2][rq][sl], (double)d2);
+            }
+        }
+      } else {
         int qn = 0;
         const int l0 = lane % cnt;
         for (int j = 0; j < cnt; ++j) {
@@ -559,24 +690,25 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
                 atomicAdd(&acc[1][tt], (double)c1);
                 atomicAdd(&acc[2][tt], (double)c2);
                 const int rq = tt >> 4, sq = e >> 6;
-                atomicAdd(&racc[rq][0][sq], (double)d0);
-                atomicAdd(&racc[rq][1][sq], (double)d1);
-                atomicAdd(&racc[rq][2][sq], (double)d2);
+                atomicAdd(&racc[0][rq][sq], (double)d0);
+                atomicAdd(&racc[1][rq][sq], (double)d1);
+                atomicAdd(&racc[2][rq][sq], (double)d2);
             }
         }
+      }
         __syncthreads();
         // retire the cnt ring sources: their source-side sums go to u^N
         if (lane < cnt) {
             const int slot = (rhead + lane) & (kSymRing - 1);
             double v0 = 0.0, v1 = 0.0, v2 = 0.0;
 #pragma unroll
-            for (int rq = 0; rq < 4; ++rq) {
-                v0 += racc[rq][0][lane];
-                v1 += racc[rq][1][lane];
-                v2 += racc[rq][2][lane];
-                racc[rq][0][lane] = 0.0;
-                racc[rq][1][lane] = 0.0;
-                racc[rq][2][lane] = 0.0;
+            for (int rq = 0; rq < kCp; ++rq) {
+                v0 += racc[0][rq][lane];
+                v1 += racc[1][rq][lane];
+                v2 += racc[2][rq][lane];
+                racc[0][rq][lane] = 0.0;
+                racc[1][rq][lane] = 0.0;
+                racc[2][rq][lane] = 0.0;
             }
             if (v0 != 0.0 || v1 != 0.0 || v2 != 0.0) {
                 const int64_t jj = ringk[slot] & (kFar - 1);
@@ -651,10 +783,10 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
                         }
                         rcount += __popcll(bm);
                         __syncthreads();
-                        while (rcount >= kSymTest) {
-                            process(kSymTest);
-                            rhead = (rhead + kSymTest) & (kSymRing - 1);
-                            rcount -= kSymTest;
+                        while (rcount >= kB) {
+                            process(kB);
+                            rhead = (rhead + kB) & (kSymRing - 1);
+                            rcount -= kB;
                         }
                     }
                 }
@@ -662,15 +794,15 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
         }
     }
     while (rcount > 0) {
-        const int c = rcount < kSymTest ? rcount : kSymTest;
+        const int c = rcount < kB ? rcount : kB;
         process(c);
         rhead = (rhead + c) & (kSymRing - 1);
         rcount -= c;
     }
     if (active) {
-        unsafeAtomicAdd(&u_near[i], acc[0][lane]);
-        unsafeAtomicAdd(&u_near[(int64_t)n + i], acc[1][lane]);
-        unsafeAtomicAdd(&u_near[2 * (int64_t)n + i], acc[2][lane]);
+        unsafeAtomicAdd(&u_near[i], acc[0][lane] + oacc[0]);
+        unsafeAtomicAdd(&u_near[(int64_t)n + i], acc[1][lane] + oacc[1]);
+        unsafeAtomicAdd(&u_near[2 * (int64_t)n + i], acc[2][lane] + oacc[2]);
     }
 }
 
