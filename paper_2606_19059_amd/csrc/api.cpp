@@ -669,10 +669,6 @@ int ewald_plan_create(const ewald_params* params, ewald_plan_t* plan_out)
     if (rc == EWALD_OK) {
         hipError_t e = hipGetDevice(&pl->device);
         if (e != hipSuccess) rc = hip_fail(e, "hipGetDevice");
-        if (rc == EWALD_OK) {
-            e = hipDeviceGetAttribute(&pl->lds_per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, pl->device);
-            if (e != hipSuccess) rc = hip_fail(e, "hipDeviceGetAttribute");
-        }
     }
     if (rc == EWALD_OK) rc = build_tables(pl);
     if (rc == EWALD_OK && pl->timers) {

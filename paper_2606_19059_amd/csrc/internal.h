@@ -79,7 +79,6 @@ struct Plan {
     bool stresslet;        // workspace sized for combined Stokeslet + stresslet sources
     bool timers;
     int device;
-    int lds_per_block;     // device limit on LDS bytes per workgroup
     // device tables owned by the plan
     void* d_tables;        // one allocation holding everything below
     double* d_cnv[3];      // per-axis CNV factors E_d[k] (FP64), lengths M1, M2, M3/2

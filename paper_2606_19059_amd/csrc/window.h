@@ -80,7 +80,8 @@ inline WinArgs<T> make_win_args(const Plan& pl)
     return wa;
 }
 
-__device__ inline int wrapi(int a, int M) { return ((a % M) + M) % M; }
+// periodic wrap of a grid index; grid sizes are powers of two (checked when a plan is made)
+__device__ inline int wrapi(int a, int M) { return a & (M - 1); }
 __device__ inline int floor_div(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
 
 // Cell, fraction and force of a sorted record, in the kernel's precision T.

@@ -345,16 +345,16 @@ def test_largest_grid():
     assert err <= 1e-4
 
 
-def test_tiled_g2p_on_a_large_grid():
-    """Grids above 128 MB use the LDS-tiled G2P; its three paths (components staged together,
-    one at a time, direct gathers) against the spectral oracle's far field.  Particles: a tight
-    cluster, a looser one and a uniform sprinkle, so the 32-target groups span small, medium
-    and large regions."""
+def test_g2p_on_a_large_grid_with_clusters():
+    """G2P on a 256^3 grid (three precisions) against the spectral oracle's far field.
+    Particles: a tight cluster, a looser one, one straddling the periodic corner (stencil runs
+    that cross the z boundary take the element-wise loads) and a uniform sprinkle, so the
+    16-target groups span small, medium and large regions."""
     E = _E()
     box, grid, xi, P = (1.0, 1.0, 1.0), (256, 256, 256), 60.0, 8
     rng = np.random.default_rng(31)
     x = np.concatenate([0.3 + 0.01 * rng.random((3, 1500)), 0.6 + 0.05 * rng.random((3, 1000)),
-                        rng.random((3, 500))], axis=1)
+                        (0.995 + 0.01 * rng.random((3, 300))) % 1.0, rng.random((3, 500))], axis=1)
     f = rng.standard_normal((3, x.shape[1]))
     m = 0.94 * math.sqrt(math.pi * P)
     ref = S.far_field(x, f, box, grid, xi, P, m)
