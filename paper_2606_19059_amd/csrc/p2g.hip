@@ -130,20 +130,19 @@ __global__ __launch_bounds__(kWaves * 64) void k_p2g_sweep(const typename RecVie
                     sf[q][d] = f[d];
                     st[q][d] = t[d];
                 }
-                if (!wa.kb) {
-                    // Gaussian: two exponentials and P products per axis on the staging lane
-                    T wv[P];
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        window_weights<T, P>(t[d], wa, wv);
-#pragma unroll
-                        for (int k = 0; k < P; ++k) sw[q][d][k] = wv[k];
-                    }
-                }
             }
-            if (wa.kb) {
+            __syncthreads();
+            if (!wa.kb) {
+                // Gaussian: one lane per (particle, axis), two exponentials and P products
+                if (lane < 3 * cnt) {
+                    const int qq = q0 + lane / 3, d = lane % 3;
+                    T wv[P];
+                    window_weights<T, P>(st[qq][d], wa, wv);
+#pragma unroll
+                    for (int k = 0; k < P; ++k) sw[qq][d][k] = wv[k];
+                }
+            } else {
                 // Kaiser-Bessel: one polynomial per weight, spread over all lanes of the wave
-                __syncthreads();
                 for (int k = lane; k < cnt * 3 * P; k += kWave) {
                     const int qq = q0 + k / (3 * P), d = (k / P) % 3, j = k % P;
                     sw[qq][d][j] = window_weight_one<T, P>(j, st[qq][d], wa);

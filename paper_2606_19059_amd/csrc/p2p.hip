@@ -307,7 +307,7 @@ __global__ __launch_bounds__(64) void k_p2p(int n, const Rec64* __restrict__ rec
     const Rec64 me = rec[active ? i : first];
 
     const int tc[3] = {t / (g.NT[1] * g.NT[2]), (t / g.NT[2]) % g.NT[1], t % g.NT[2]};
-    double w[3], blo[3], bhi[3], tx[3], oacc[3];
+    double w[3], blo[3], bhi[3], tx[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         w[d] = g.B * g.h[d];
@@ -447,8 +447,9 @@ __global__ __launch_bounds__(64) void k_p2p(int n, const Rec64* __restrict__ rec
 // per lane; a lane keeps up to R pairs of its own target (summed in registers) and puts
 // the rest in a queue, from which lanes with fewer than R pairs take work in their spare
 // rounds (target side by LDS atomics, about 15% of the pairs at uniform density).  Lanes
-// take their own sources in an order rotated by lane mod 32, so that the 32 lanes sharing
-// one copy of the batch's source accumulators meet different sources in a round.
+// take their own sources in an order rotated by lane mod 32, so that lanes t and t + 32
+// aside, the lanes meet different sources in a round when their masks are full (fewer
+// collisions on the batch's source accumulators).
 //
 // Stresslet form (queue drain): candidates are tested in diagonal order (lane t tests
 // ring source (t + j) mod 16 at step j), so that the queued pairs of one drain round have
@@ -458,10 +459,11 @@ __global__ __launch_bounds__(64) void k_p2p(int n, const Rec64* __restrict__ rec
 constexpr int kSymRing = 64;
 constexpr int kSymTest = 16;
 constexpr int kFar = 1 << 30;  // ring key offset of sources outside the targets' own tile
-// Balanced (Stokeslet-only) form: batches of 32 ring entries, source accumulators in two
-// copies (lanes 0-31 and 32-63).  Queue bound: with c_t <= 32 pairs per lane, Q = sum c_t
-// and R = ceil(Q / 64) rounds, the excess sum over c_t >= R of (c_t - R) is at most
-// Q (32 - R) / 32 <= 2 R (32 - R) <= 512.
+// Balanced (Stokeslet-only) form: batches of 32 ring entries and one copy of the source
+// accumulators (a second copy, for lanes 32-63, was measured 2% slower: the LDS it takes
+// costs more occupancy than the atomic collisions it saves).  Queue bound: with c_t <= 32
+// pairs per lane, Q = sum c_t and R = ceil(Q / 64) rounds, the excess sum over c_t >= R
+// of (c_t - R) is at most Q (32 - R) / 32 <= 2 R (32 - R) <= 512.
 constexpr int kBalBatch = 32;
 constexpr int kBalExcess = 512;
 static_assert(kBalBatch == 32 && kSymRing == 64, "the mask, ring and queue sizes assume 32-entry batches");
@@ -495,7 +497,7 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
     __shared__ int ringk[kSymRing];
     // batch size and copies of the per-batch source accumulators (per component, copy, entry)
     constexpr int kB = ST ? kSymTest : kBalBatch;
-    constexpr int kCp = ST ? 4 : 2;
+    constexpr int kCp = ST ? 4 : 1;
     __shared__ double racc[3][kCp][kB];
     __shared__ unsigned short queue[ST ? kSymTest * kWave : kBalExcess];
     static_assert(kSymRing == kWave, "one ring slot per lane");
@@ -531,7 +533,7 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
         tgt[d][lane] = tx[d];
         tgtf[d][lane] = (TF)me.f[d];
         acc[d][lane] = 0.0;
-        racc[d][lane / kB][lane % kB] = 0.0;
+        if (lane < kCp * kB) racc[d][lane / kB][lane % kB] = 0.0;
         oacc[d] = 0.0;
     }
     if (ST) {
@@ -573,9 +575,8 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
         }
         const int rounds = (qn + kWave - 1) / kWave;
         // 2. a lane keeps up to `rounds` of its target's pairs (taken in an order rotated by
-        //    lane mod 32, so that the lanes sharing a copy of the source accumulators meet
-        //    different sources in a round); the excess goes to the queue, for lanes that run
-        //    out of pairs of their own
+        //    lane mod 32, to spread a round's sources); the excess goes to the queue, for
+        //    lanes that run out of pairs of their own
         const int rot = lane & (kB - 1);
         const unsigned rm0 = rot ? ((m >> rot) | (m << (kB - rot))) : m;
         unsigned rm = rm0;
@@ -598,8 +599,7 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
         __syncthreads();
         // 3. `rounds` rounds, one pair per lane: the lane's own target while it has pairs
         //    (target side summed in registers), then queue entries in order (target side by
-        //    LDS atomics); the source side goes to this lane quarter's copy of the batch
-        //    accumulators
+        //    LDS atomics); the source side goes to the batch's source accumulators
         int qb = 0;
         for (int r = 0; r < rounds; ++r) {
             // branch-free round: every lane reads a queue entry (in range, used only by
@@ -634,7 +634,7 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
                 atomicAdd(&acc[2][tt], (double)c2);
             }
             if (own || don) {
-                const int rq = lane / kB;
+                const int rq = lane / (kWave / kCp);
                 atomicAdd(&racc[0][rq][sl], (double)d0);
                 atomicAdd(&racc[1][rq][sl], (double)d1);
                 atomicAdd(&racc[2][rq][sl], (double)d2);
