@@ -198,10 +198,10 @@ struct CostModel {
     double fft_cell, fft0;
     double sort, sort_cell, sort0;
 };
-constexpr CostModel kCost64 = {8.85, 0.50, 0.316, 0.205, 0.105, 1.349, 0.330, 0.153, 0.092, 0.111, 0.030,
-                               0.186, 0.011, 0.052};
-constexpr CostModel kCost32 = {6.92, 0.77, 0.386, 0.193, 0.163, 1.473, 0.0, 0.021, 0.048, 0.081, 0.038,
-                               0.208, 0.008, 0.053};
+constexpr CostModel kCost64 = {7.488, 0.339, 0.295, 0.162, 0.086, 1.025, 0.032, 0.107, 0.061, 0.110, 0.030,
+                               0.208, 0.009, 0.043};
+constexpr CostModel kCost32 = {6.394, 0.573, 0.348, 0.140, 0.150, 0.872, 0.0, 0.002, 0.030, 0.081, 0.038,
+                               0.196, 0.011, 0.054};
 constexpr double kWaveSlots = 1536.0;  // concurrent P2P waves at which the chip is full
 
 int p2g_blocks(const int M[3], int P)
