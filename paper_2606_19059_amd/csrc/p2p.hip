@@ -484,7 +484,7 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
                                                 const double* __restrict__ srec,
                                                 const int* __restrict__ start,
                                                 const int* __restrict__ chunk_off, Geometry g,
-                                                PairArgs a, double* __restrict__ u_near)
+                                                PairArgs a, double* __restrict__ u_near, int nsplit)
 {
     constexpr int NS = ST ? 6 : 1;
     __shared__ double tgt[3][kWave];
@@ -504,7 +504,10 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
 
     // plain block order: an XCD-aware order (each XCD sweeping a contiguous range) was
     // measured 12% slower here, unlike in G2P
-    const int wave = uniform_i((int)blockIdx.x);
+    // nsplit waves share a chunk, each taking every nsplit-th of its neighbour tiles (shorter
+    // waves: a smaller tail when the last waves of the launch run)
+    const int wave = uniform_i((int)blockIdx.x) / nsplit;
+    const int part = uniform_i((int)blockIdx.x) % nsplit;
     const int lane = threadIdx.x;
     const int total = chunk_off[g.ntiles];
     if (wave >= total) return;
@@ -544,6 +547,7 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
     __syncthreads();
 
     int rhead = 0, rcount = 0;
+    int tk = 0;  // neighbour tiles met so far (those within r_c of the targets)
 
     auto process = [&](int cnt) {
       if constexpr (!ST) {
@@ -740,6 +744,7 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
                 const double shz = fz * g.L[2];
                 const double gz = fmax(0.0, fmax(uz * w[2] - bhi[2], blo[2] - (uz + 1) * w[2]));
                 if (gx * gx + gy * gy + gz * gz >= a.rc2) continue;
+                if (tk++ % nsplit != part) continue;  // another wave of this chunk takes it
                 const bool own = (dx == 0 && dy == 0 && dz == 0);
                 const int nt = (wx * g.NT[1] + wy) * g.NT[2] + wz;
                 // own tile: sources below the first target can pair with none of them
@@ -846,30 +851,36 @@ hipError_t launch_p2p(const Plan& pl, const Work& w, int n, hipStream_t s, bool 
                                pl.g, a, w.u_near);
         return hipGetLastError();
     }
+    // Symmetric kernel: with few chunks per wave slot of the chip (c2: 15.6k chunks, about 4 per
+    // slot), three waves per chunk shorten the waves and so the launch's tail (measured at c2:
+    // 25.5 -> 24.2 ms; two: 24.5, four: 25.3); with many (c3: 156k) one (two and four were
+    // slower there).
+    const int kSplit = waves < 40000 ? 3 : 1;
+    const dim3 sgrid((unsigned)(waves * kSplit));
     const int64_t cnt = 3 * (int64_t)n;
     hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, w.u_near, cnt);
     const double* sr = w.srec;
     if (st) {
         if (f64 && fast)
-            hipLaunchKernelGGL((k_p2p_sym<double, true, true>), grid, block, 0, s, n, rec, sr, w.start, w.chunk_off,
-                               pl.g, a, w.u_near);
+            hipLaunchKernelGGL((k_p2p_sym<double, true, true>), sgrid, block, 0, s, n, rec, sr, w.start, w.chunk_off,
+                               pl.g, a, w.u_near, kSplit);
         else if (f64)
-            hipLaunchKernelGGL((k_p2p_sym<double, false, true>), grid, block, 0, s, n, rec, sr, w.start,
-                               w.chunk_off, pl.g, a, w.u_near);
+            hipLaunchKernelGGL((k_p2p_sym<double, false, true>), sgrid, block, 0, s, n, rec, sr, w.start,
+                               w.chunk_off, pl.g, a, w.u_near, kSplit);
         else
-            hipLaunchKernelGGL((k_p2p_sym<float, false, true>), grid, block, 0, s, n, rec, sr, w.start,
-                               w.chunk_off, pl.g, a, w.u_near);
+            hipLaunchKernelGGL((k_p2p_sym<float, false, true>), sgrid, block, 0, s, n, rec, sr, w.start,
+                               w.chunk_off, pl.g, a, w.u_near, kSplit);
         return hipGetLastError();
     }
     if (f64 && fast)
-        hipLaunchKernelGGL((k_p2p_sym<double, true, false>), grid, block, 0, s, n, rec, sr, w.start, w.chunk_off,
-                           pl.g, a, w.u_near);
+        hipLaunchKernelGGL((k_p2p_sym<double, true, false>), sgrid, block, 0, s, n, rec, sr, w.start, w.chunk_off,
+                           pl.g, a, w.u_near, kSplit);
     else if (f64)
-        hipLaunchKernelGGL((k_p2p_sym<double, false, false>), grid, block, 0, s, n, rec, sr, w.start,
-                           w.chunk_off, pl.g, a, w.u_near);
+        hipLaunchKernelGGL((k_p2p_sym<double, false, false>), sgrid, block, 0, s, n, rec, sr, w.start,
+                           w.chunk_off, pl.g, a, w.u_near, kSplit);
     else
-        hipLaunchKernelGGL((k_p2p_sym<float, false, false>), grid, block, 0, s, n, rec, sr, w.start,
-                           w.chunk_off, pl.g, a, w.u_near);
+        hipLaunchKernelGGL((k_p2p_sym<float, false, false>), sgrid, block, 0, s, n, rec, sr, w.start,
+                           w.chunk_off, pl.g, a, w.u_near, kSplit);
     return hipGetLastError();
 }
 
