@@ -439,27 +439,21 @@ __global__ __launch_bounds__(64) void k_p2p(int n, const Rec64* __restrict__ rec
 // results agree to rounding, not bitwise (the one-sided kernel above is the reproducible
 // variant).
 //
-// Stokeslet-only form (balanced drain).  LDS traffic, not arithmetic, bounds the queue
-// drain above (six LDS atomics and twelve operand loads per pair), so the target side is
-// kept in registers where possible.  Per batch of 32 ring entries each lane tests its own
-// target against all of them (a 32-bit mask; all lanes read the same entry, an LDS
-// broadcast).  With Q accepted pairs the batch takes R = ceil(Q / 64) rounds of one pair
-// per lane; a lane keeps up to R pairs of its own target (summed in registers) and puts
-// the rest in a queue, from which lanes with fewer than R pairs take work in their spare
-// rounds (target side by LDS atomics, about 15% of the pairs at uniform density).  Lanes
-// take their own sources in an order rotated by lane mod 32, so that lanes t and t + 32
-// aside, the lanes meet different sources in a round when their masks are full (fewer
-// collisions on the batch's source accumulators).
-//
-// Stresslet form (queue drain): candidates are tested in diagonal order (lane t tests
-// ring source (t + j) mod 16 at step j), so that the queued pairs of one drain round have
-// distinct targets; the four targets t, t + 16, t + 32, t + 48 that share a source add
-// into separate copies of the batch's source accumulators (summed when the batch
-// retires), so neither side's LDS atomics hit one address twice in a round.
+// Balanced drain.  LDS traffic, not arithmetic, bounded an earlier form that put every
+// accepted pair through an LDS queue (six LDS atomics and twelve operand loads per pair), so
+// the target side is kept in registers where possible.  Per batch of 32 ring entries each
+// lane tests its own target against all of them (a 32-bit mask; all lanes read the same
+// entry, an LDS broadcast).  With Q accepted pairs the batch takes R = ceil(Q / 64) rounds
+// of one pair per lane; a lane keeps up to R pairs of its own target (summed in registers)
+// and puts the rest in a queue, from which lanes with fewer than R pairs take work in their
+// spare rounds (target side by LDS atomics, about 15% of the pairs at uniform density).
+// Lanes take their own sources in an order rotated by lane mod 32, so that lanes t and
+// t + 32 aside, the lanes meet different sources in a round when their masks are full
+// (fewer collisions on the batch's source accumulators).  With stresslet sources the same
+// schedule carries the stresslet pair terms as well.
 constexpr int kSymRing = 64;
-constexpr int kSymTest = 16;
 constexpr int kFar = 1 << 30;  // ring key offset of sources outside the targets' own tile
-// Balanced (Stokeslet-only) form: batches of 32 ring entries and one copy of the source
+// Balanced drain: batches of 32 ring entries and one copy of the source
 // accumulators (a second copy, for lanes 32-63, was measured 2% slower: the LDS it takes
 // costs more occupancy than the atomic collisions it saves).  Queue bound: with c_t <= 32
 // pairs per lane, Q = sum c_t and R = ceil(Q / 64) rounds, the excess sum over c_t >= R
@@ -496,10 +490,10 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
     __shared__ TF ringf[3][kSymRing];
     __shared__ int ringk[kSymRing];
     // batch size and copies of the per-batch source accumulators (per component, copy, entry)
-    constexpr int kB = ST ? kSymTest : kBalBatch;
-    constexpr int kCp = ST ? 4 : 1;
+    constexpr int kB = kBalBatch;
+    constexpr int kCp = 1;
     __shared__ double racc[3][kCp][kB];
-    __shared__ unsigned short queue[ST ? kSymTest * kWave : kBalExcess];
+    __shared__ unsigned short queue[kBalExcess];
     static_assert(kSymRing == kWave, "one ring slot per lane");
 
     // plain block order: an XCD-aware order (each XCD sweeping a contiguous range) was
@@ -550,7 +544,6 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
     int tk = 0;  // neighbour tiles met so far (those within r_c of the targets)
 
     auto process = [&](int cnt) {
-      if constexpr (!ST) {
         // 1. test: bit j of m is set when this lane's target pairs with batch entry j (all
         //    lanes read the same entry: LDS broadcast)
         //    Sources of other tiles are never at r = 0 and always follow the wave's own
@@ -624,9 +617,24 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
             const double rz = tgt[2][tt] - ring[2][slot];
             const double r2 = rx * rx + ry * ry + rz * rz;
             TF a1, b, c0, c1, c2, d0, d1, d2;
-            Coef<TF, Fast>::eval(r2, a, a1, b);
-            apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, ringf[0][slot], ringf[1][slot], ringf[2][slot], c0, c1, c2);
-            apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, tgtf[0][tt], tgtf[1][tt], tgtf[2][tt], d0, d1, d2);
+            if constexpr (ST) {
+                TF al, be;
+                CoefSt<TF, Fast>::eval(r2, a, a1, b, al, be);
+                apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, ringf[0][slot], ringf[1][slot], ringf[2][slot], c0, c1, c2);
+                apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, tgtf[0][tt], tgtf[1][tt], tgtf[2][tt], d0, d1, d2);
+                TF ss[6], st[6];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    ss[c] = rings[c][slot];
+                    st[c] = -tgts[c][tt];  // T^N(-r) = -T^N(r)
+                }
+                apply_st<TF>(al, be, (TF)rx, (TF)ry, (TF)rz, ss, c0, c1, c2);
+                apply_st<TF>(al, be, (TF)rx, (TF)ry, (TF)rz, st, d0, d1, d2);
+            } else {
+                Coef<TF, Fast>::eval(r2, a, a1, b);
+                apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, ringf[0][slot], ringf[1][slot], ringf[2][slot], c0, c1, c2);
+                apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, tgtf[0][tt], tgtf[1][tt], tgtf[2][tt], d0, d1, d2);
+            }
             if (own) {
                 oacc[0] += (double)c0;
                 oacc[1] += (double)c1;
@@ -644,62 +652,6 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
                 atomicAdd(&racc[2][rq][sl], (double)d2);
             }
         }
-      } else {
-        int qn = 0;
-        const int l0 = lane % cnt;
-        for (int j = 0; j < cnt; ++j) {
-            int sl = l0 + j;
-            if (sl >= cnt) sl -= cnt;
-            const int slot = (rhead + sl) & (kSymRing - 1);
-            const double rx = tx[0] - ring[0][slot], ry = tx[1] - ring[1][slot], rz = tx[2] - ring[2][slot];
-            const double r2 = rx * rx + ry * ry + rz * rz;
-            const bool pass = (r2 < a.rc2) && (r2 > 0.0) && (ringk[slot] > i);
-            const unsigned long long b = __ballot(pass);
-            if (pass) queue[qn + lanes_below(b)] = (unsigned short)(lane | (sl << 6));
-            qn += __popcll(b);
-        }
-        __syncthreads();
-        for (int q0 = 0; q0 < qn; q0 += kWave) {
-            const int k = q0 + lane;
-            if (k < qn) {
-                const int e = queue[k];
-                const int tt = e & (kWave - 1);
-                const int slot = (rhead + (e >> 6)) & (kSymRing - 1);
-                const double rx = tgt[0][tt] - ring[0][slot];
-                const double ry = tgt[1][tt] - ring[1][slot];
-                const double rz = tgt[2][tt] - ring[2][slot];
-                const double r2 = rx * rx + ry * ry + rz * rz;
-                TF a1, b, c0, c1, c2, d0, d1, d2;
-                if (ST) {
-                    TF al, be;
-                    CoefSt<TF, Fast>::eval(r2, a, a1, b, al, be);
-                    apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, ringf[0][slot], ringf[1][slot], ringf[2][slot], c0, c1,
-                              c2);
-                    apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, tgtf[0][tt], tgtf[1][tt], tgtf[2][tt], d0, d1, d2);
-                    TF ss[6], st[6];
-#pragma unroll
-                    for (int c = 0; c < 6; ++c) {
-                        ss[c] = rings[c % NS][slot];
-                        st[c] = -tgts[c % NS][tt];  // T^N(-r) = -T^N(r)
-                    }
-                    apply_st<TF>(al, be, (TF)rx, (TF)ry, (TF)rz, ss, c0, c1, c2);
-                    apply_st<TF>(al, be, (TF)rx, (TF)ry, (TF)rz, st, d0, d1, d2);
-                } else {
-                    Coef<TF, Fast>::eval(r2, a, a1, b);
-                    apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, ringf[0][slot], ringf[1][slot], ringf[2][slot], c0, c1,
-                              c2);
-                    apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, tgtf[0][tt], tgtf[1][tt], tgtf[2][tt], d0, d1, d2);
-                }
-                atomicAdd(&acc[0][tt], (double)c0);
-                atomicAdd(&acc[1][tt], (double)c1);
-                atomicAdd(&acc[2][tt], (double)c2);
-                const int rq = tt >> 4, sq = e >> 6;
-                atomicAdd(&racc[0][rq][sq], (double)d0);
-                atomicAdd(&racc[1][rq][sq], (double)d1);
-                atomicAdd(&racc[2][rq][sq], (double)d2);
-            }
-        }
-      }
         __syncthreads();
         // retire the cnt ring sources: their source-side sums go to u^N
         if (lane < cnt) {
