@@ -26,6 +26,16 @@ constexpr int kPerWave = 16;  // particles staged per wave and round
 constexpr int kChunk = kWaves * kPerWave;
 constexpr int kMaxRuns = 320; // runs per slab (window rows x z-tile segments)
 
+// LDS hand-off between the lanes of one wavefront (the staged particles of a chunk are
+// private to the wave that stages and spreads them, so the waves of a block need not wait
+// for each other there): orders the wave's LDS accesses before and after it
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // T: arithmetic and accumulation precision; TG: grid element type (the FP32 bulk mode
 // accumulates in FP64 -- the same VALU rate as FP32 without packed math -- and stores FP32).
 // A block of kWaves waves owns one (patch, x-segment): every wave keeps accumulators for
@@ -131,7 +141,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_p2g_sweep(const typename RecVie
                     st[q][d] = t[d];
                 }
             }
-            __syncthreads();
+            wave_lds_sync();
             if (!wa.kb) {
                 // Gaussian: one lane per (particle, axis), two exponentials and P products
                 if (lane < 3 * cnt) {
@@ -148,7 +158,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_p2g_sweep(const typename RecVie
                     sw[qq][d][j] = window_weight_one<T, P>(j, st[qq][d], wa);
                 }
             }
-            __syncthreads();
+            wave_lds_sync();
             for (int q = q0; q < q0 + cnt; ++q) {
                 const int off = soff[q];
                 const int ky = ly - ((off & 255) - P);
@@ -166,7 +176,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_p2g_sweep(const typename RecVie
                     acc[k][2] += wx * g2;
                 }
             }
-            __syncthreads();
+            wave_lds_sync();
         }
 
         const int xo = cxu - P / 2 + 1;
