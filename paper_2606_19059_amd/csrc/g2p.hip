@@ -17,16 +17,18 @@ namespace ewald {
 
 namespace {
 
-// One wavefront per kG2PPerWave consecutive (cell-sorted) targets, all at once: target q
-// of the group has lanes 4q .. 4q + 3.  A lane item is a footprint row y and a run of V
-// consecutive z (one 16-byte load per item and x-plane, 8-byte for FP32 grids whose P is
-// not a multiple of 4); the lanes of a target step through its P * P / V items and walk
-// the P x-planes of each.  The wave's loads of one step touch the union of 16 neighbouring
-// footprints, which is a small multiple of one footprint (measured at N = 1e6, 128^3, FP64,
-// P = 16: 5.8 ms with one target per wave at a time, 3.3 ms with 16).  The 3 x P 1D
-// weights of every target are computed once (one lane per weight) and shared through LDS;
-// each target's four partial sums are reduced with shuffles.
-constexpr int kG2PPerWave = 16;
+// One wavefront per group of consecutive (cell-sorted) targets, all at once: 16 targets of
+// four lanes each for FP64 grids, 32 of two lanes for FP32 grids (measured fastest: FP64 at
+// P = 16 and 14 with 16, FP32 at P = 12 and 10 with 32).  A lane item is a footprint row y
+// and a run of V consecutive z (one 16-byte load per item and x-plane, 8-byte for FP32
+// grids whose P is not a multiple of 4); the lanes of a target step through its P * P / V
+// items and walk the P x-planes of each.  The wave's loads of one step touch the union of
+// the group's neighbouring footprints, which is a small multiple of one footprint
+// (measured at N = 1e6, 128^3, FP64, P = 16: 5.8 ms with one target per wave at a time,
+// 3.3 ms with 16).  The 3 x P 1D weights of every target are computed once (one lane per
+// weight) and shared through LDS; each target's partial sums are reduced with shuffles.
+template <typename TG>
+constexpr int g2p_per_wave() { return sizeof(TG) == 4 ? 32 : 16; }
 
 // V consecutive grid values.  Runs start at any element, so the alignment is only that of
 // the element; gfx950 global loads accept such multi-dword accesses (the compiler emits
@@ -46,8 +48,6 @@ struct GVec<float, 4> {
     typedef float type __attribute__((ext_vector_type(4), aligned(4)));
 };
 
-constexpr int kG2PGroup = 16;  // targets gathered together (kG2PPerWave is a multiple)
-constexpr int kG2PLanes = kWave / kG2PGroup;
 
 template <typename T, typename TG, int P>
 __global__ __launch_bounds__(64) void k_g2p(int n, const typename RecView<T>::Rec* __restrict__ rec,
@@ -62,6 +62,8 @@ __global__ __launch_bounds__(64) void k_g2p(int n, const typename RecView<T>::Re
     constexpr int V = (sizeof(TG) == 8 || P % 4 != 0) ? 2 : 4;
     constexpr int G = P / V;
     constexpr int kItems = P * G;
+    constexpr int kG2PGroup = g2p_per_wave<TG>();  // targets gathered together
+    constexpr int kG2PLanes = kWave / kG2PGroup;   // lanes per target
     constexpr int kPass = (kItems + kG2PLanes - 1) / kG2PLanes;
     constexpr int kU = (P % 4 == 0) ? 4 : 2;  // x-planes per batch of loads (divides P)
     using VT = typename GVec<TG, V>::type;
@@ -69,7 +71,7 @@ __global__ __launch_bounds__(64) void k_g2p(int n, const typename RecView<T>::Re
     __shared__ int anc[kG2PGroup][3];
     const int lane = threadIdx.x;
     const int q = lane / kG2PLanes, ql = lane % kG2PLanes;  // target of the group, lane within it
-    static_assert(kG2PPerWave % kG2PGroup == 0 && kWave % kG2PGroup == 0, "whole groups of lanes and targets");
+    static_assert(kWave % kG2PGroup == 0, "whole groups of lanes");
     const int M1 = g.M[0], M2 = g.M[1], M3 = g.M[2];
     const int64_t nc = g.ncells;
     // 32-bit offsets within one component (at most 512^3 points)
@@ -78,8 +80,8 @@ __global__ __launch_bounds__(64) void k_g2p(int n, const typename RecView<T>::Re
     const TG* __restrict__ g1 = grid + nc;
     const TG* __restrict__ g2 = grid + 2 * nc;
     const int64_t nn = n;
-    const int s0 = xcd_remap((int)blockIdx.x, (int)gridDim.x) * kG2PPerWave;
-    const int s1 = min(s0 + kG2PPerWave, n);
+    const int s0 = xcd_remap((int)blockIdx.x, (int)gridDim.x) * kG2PGroup;
+    const int s1 = min(s0 + kG2PGroup, n);
     for (int sg = s0; sg < s1; sg += kG2PGroup) {
         // weights and stencil anchors of the group's targets (missing targets repeat the last)
         for (int k = lane; k < kG2PGroup * 3 * P; k += kWave) {
@@ -181,7 +183,8 @@ hipError_t launch_g2p_t(const Plan& pl, const Work& w, int n, const double* f, d
                         double* uf, hipStream_t s)
 {
     const double self_coef = 4.0 * pl.xi / sqrt(M_PI);
-    hipLaunchKernelGGL((k_g2p<T, TG, P>), dim3((n + kG2PPerWave - 1) / kG2PPerWave), dim3(kWave), 0, s, n,
+    constexpr int per_wave = g2p_per_wave<TG>();
+    hipLaunchKernelGGL((k_g2p<T, TG, P>), dim3((n + per_wave - 1) / per_wave), dim3(kWave), 0, s, n,
                        (const typename RecView<T>::Rec*)w.rec, (const TG*)w.grid, pl.g, make_win_args<T>(pl),
                        self_coef, w.u_near, f, u, un, uf);
     return hipGetLastError();
