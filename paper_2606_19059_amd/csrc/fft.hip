@@ -42,11 +42,11 @@ template <typename T>
 __device__ inline C2<T> csub(C2<T> a, C2<T> b) { return {a.x - b.x, a.y - b.y}; }
 
 // Batched Stockham FFT of ncomp x ncols columns of length n stored as
-// a[(comp * n + e) * ncols + c] (n and ncols powers of two).  sign = -1 forward, +1
+// a[(comp * n + e) * ld + c] (n and ncols powers of two, ld >= ncols the row stride).  sign = -1 forward, +1
 // inverse (unnormalised).  `b` is scratch of the same size.  Returns the buffer holding
 // the result (a or b).  All threads of the block take part; ends with a barrier.
 template <typename T>
-__device__ C2<T>* lds_fft(C2<T>* a, C2<T>* b, int n, int ncols, int ncomp, int sign,
+__device__ C2<T>* lds_fft(C2<T>* a, C2<T>* b, int n, int ncols, int ld, int ncomp, int sign,
                           const C2<T>* __restrict__ tw)
 {
     C2<T>* src = a;
@@ -69,13 +69,13 @@ __device__ C2<T>* lds_fft(C2<T>* a, C2<T>* b, int n, int ncols, int ncomp, int s
             const int i = rem >> lc;
             const int k = i & (p - 1);
             const int j = (i - k) * R + k;
-            C2<T>* sp = src + (size_t)comp * n * ncols;
-            C2<T>* dp = dst + (size_t)comp * n * ncols;
+            C2<T>* sp = src + (size_t)comp * n * ld;
+            C2<T>* dp = dst + (size_t)comp * n * ld;
             if (R == 4) {
-                C2<T> u0 = sp[(i)*ncols + c];
-                C2<T> u1 = sp[(i + Tn) * ncols + c];
-                C2<T> u2 = sp[(i + 2 * Tn) * ncols + c];
-                C2<T> u3 = sp[(i + 3 * Tn) * ncols + c];
+                C2<T> u0 = sp[(i)*ld + c];
+                C2<T> u1 = sp[(i + Tn) * ld + c];
+                C2<T> u2 = sp[(i + 2 * Tn) * ld + c];
+                C2<T> u3 = sp[(i + 3 * Tn) * ld + c];
                 if (k) {
                     C2<T> w1 = tw[(k * tws) & (n - 1)];
                     C2<T> w2 = tw[(2 * k * tws) & (n - 1)];
@@ -92,20 +92,20 @@ __device__ C2<T>* lds_fft(C2<T>* a, C2<T>* b, int n, int ncols, int ncomp, int s
                 const C2<T> t0 = cadd(u0, u2), t1 = csub(u0, u2), t2 = cadd(u1, u3), d = csub(u1, u3);
                 // forward: -i d ; inverse: +i d
                 const C2<T> rot = (sign < 0) ? C2<T>{d.y, -d.x} : C2<T>{-d.y, d.x};
-                dp[(j)*ncols + c] = cadd(t0, t2);
-                dp[(j + p) * ncols + c] = cadd(t1, rot);
-                dp[(j + 2 * p) * ncols + c] = csub(t0, t2);
-                dp[(j + 3 * p) * ncols + c] = csub(t1, rot);
+                dp[(j)*ld + c] = cadd(t0, t2);
+                dp[(j + p) * ld + c] = cadd(t1, rot);
+                dp[(j + 2 * p) * ld + c] = csub(t0, t2);
+                dp[(j + 3 * p) * ld + c] = csub(t1, rot);
             } else {
-                C2<T> u0 = sp[(i)*ncols + c];
-                C2<T> u1 = sp[(i + Tn) * ncols + c];
+                C2<T> u0 = sp[(i)*ld + c];
+                C2<T> u1 = sp[(i + Tn) * ld + c];
                 if (k) {
                     C2<T> w1 = tw[(k * tws) & (n - 1)];
                     if (sign > 0) w1.y = -w1.y;
                     u1 = cmul(u1, w1);
                 }
-                dp[(j)*ncols + c] = cadd(u0, u1);
-                dp[(j + p) * ncols + c] = csub(u0, u1);
+                dp[(j)*ld + c] = cadd(u0, u1);
+                dp[(j + p) * ld + c] = csub(u0, u1);
             }
         }
         __syncthreads();
@@ -125,8 +125,12 @@ __global__ __launch_bounds__(256) void k_fft_z(T* __restrict__ grid, int64_t nce
                                                const C2<T>* __restrict__ tw_full)
 {
     extern __shared__ unsigned char smem_raw[];
+    // rows padded to ncols + 1 elements: a line's consecutive elements, which consecutive
+    // threads load and store, then fall in different LDS banks (with a power-of-two row
+    // stride they would all hit a few banks)
+    const int ld = ncols + 1;
     C2<T>* a = reinterpret_cast<C2<T>*>(smem_raw);
-    C2<T>* b = a + (size_t)H * ncols;
+    C2<T>* b = a + (size_t)H * ld;
     C2<T>* data = reinterpret_cast<C2<T>*>(grid + blockIdx.y * ncells);
     const int line0 = blockIdx.x * ncols;
     const int tot = H * ncols;
@@ -134,16 +138,16 @@ __global__ __launch_bounds__(256) void k_fft_z(T* __restrict__ grid, int64_t nce
     if (sign < 0) {
         for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
             const int c = idx / H, e = idx - c * H;
-            if (line0 + c < nlines) a[e * ncols + c] = data[(int64_t)(line0 + c) * H + e];
-            else a[e * ncols + c] = C2<T>{0, 0};
+            if (line0 + c < nlines) a[e * ld + c] = data[(int64_t)(line0 + c) * H + e];
+            else a[e * ld + c] = C2<T>{0, 0};
         }
         __syncthreads();
-        C2<T>* C = lds_fft<T>(a, b, H, ncols, 1, -1, tw_half);
+        C2<T>* C = lds_fft<T>(a, b, H, ncols, ld, 1, -1, tw_half);
         for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
             const int c = idx / H, k = idx - c * H;
             if (line0 + c >= nlines) continue;
-            const C2<T> ck = C[k * ncols + c];
-            const C2<T> cm0 = C[((H - k) & (H - 1)) * ncols + c];
+            const C2<T> ck = C[k * ld + c];
+            const C2<T> cm0 = C[((H - k) & (H - 1)) * ld + c];
             const C2<T> cm = {cm0.x, -cm0.y};
             const C2<T> E = {(T)0.5 * (ck.x + cm.x), (T)0.5 * (ck.y + cm.y)};
             const C2<T> dd = csub(ck, cm);
@@ -153,32 +157,32 @@ __global__ __launch_bounds__(256) void k_fft_z(T* __restrict__ grid, int64_t nce
     } else {
         for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
             const int c = idx / H, e = idx - c * H;
-            if (line0 + c < nlines) b[e * ncols + c] = data[(int64_t)(line0 + c) * H + e];
-            else b[e * ncols + c] = C2<T>{0, 0};
+            if (line0 + c < nlines) b[e * ld + c] = data[(int64_t)(line0 + c) * H + e];
+            else b[e * ld + c] = C2<T>{0, 0};
         }
         __syncthreads();
         for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
             const int c = idx / H, k = idx - c * H;
-            C2<T> xk = b[k * ncols + c];
+            C2<T> xk = b[k * ld + c];
             C2<T> xm;
             if (k == 0) {
                 xk.y = 0;             // DC of a real line
                 xm = C2<T>{0, 0};     // Nyquist (zeroed by CNV)
             } else {
-                const C2<T> v = b[(H - k) * ncols + c];
+                const C2<T> v = b[(H - k) * ld + c];
                 xm = C2<T>{v.x, -v.y};
             }
             const C2<T> E = cadd(xk, xm);
             C2<T> w = tw_full[k];
             w.y = -w.y;  // e^{+2 pi i k / M3}
             const C2<T> O = cmul(csub(xk, xm), w);
-            a[k * ncols + c] = C2<T>{E.x - O.y, E.y + O.x};  // E + i O
+            a[k * ld + c] = C2<T>{E.x - O.y, E.y + O.x};  // E + i O
         }
         __syncthreads();
-        C2<T>* z = lds_fft<T>(a, b, H, ncols, 1, +1, tw_half);
+        C2<T>* z = lds_fft<T>(a, b, H, ncols, ld, 1, +1, tw_half);
         for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
             const int c = idx / H, e = idx - c * H;
-            if (line0 + c < nlines) data[(int64_t)(line0 + c) * H + e] = z[e * ncols + c];
+            if (line0 + c < nlines) data[(int64_t)(line0 + c) * H + e] = z[e * ld + c];
         }
     }
 }
@@ -203,7 +207,7 @@ __global__ __launch_bounds__(256) void k_fft_y(T* __restrict__ grid, int64_t nce
         a[idx] = data[base + (int64_t)e * H + c];
     }
     __syncthreads();
-    C2<T>* r = lds_fft<T>(a, b, M2, ncols, 1, sign, tw);
+    C2<T>* r = lds_fft<T>(a, b, M2, ncols, ncols, 1, sign, tw);
     for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
         const int e = idx / ncols, c = idx - e * ncols;
         data[base + (int64_t)e * H + c] = r[idx];
@@ -242,7 +246,7 @@ __global__ __launch_bounds__(256) void k_fft_x_cnv(T* __restrict__ grid, int64_t
         a[idx] = data[(int64_t)e * rowstride + (int64_t)ky * H + kz0 + c];
     }
     __syncthreads();
-    C2<T>* r = lds_fft<T>(a, b, M1, ncols, 3, -1, tw);
+    C2<T>* r = lds_fft<T>(a, b, M1, ncols, ncols, 3, -1, tw);
     if (do_cnv) {
         const int kys = (ky < M2 / 2) ? ky : ky - M2;
         const double k1 = ca.twopi_over_L[1] * kys;
@@ -268,7 +272,7 @@ __global__ __launch_bounds__(256) void k_fft_x_cnv(T* __restrict__ grid, int64_t
         }
         __syncthreads();
     }
-    if (do_inv) r = lds_fft<T>(r, (r == a) ? b : a, M1, ncols, 3, +1, tw);
+    if (do_inv) r = lds_fft<T>(r, (r == a) ? b : a, M1, ncols, ncols, 3, +1, tw);
     for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
         const int comp = idx / per, rem = idx - comp * per;
         const int e = rem / ncols, c = rem - e * ncols;
@@ -340,7 +344,7 @@ __global__ __launch_bounds__(256) void k_cnv_st_x(T* __restrict__ grid, int64_t 
         }
     }
     __syncthreads();
-    C2<T>* r = lds_fft<T>(a, b, M1, ncols, 3, +1, tw);
+    C2<T>* r = lds_fft<T>(a, b, M1, ncols, ncols, 3, +1, tw);
     const int tot = 3 * per;
     for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
         const int comp = idx / per, rem = idx - comp * per;
@@ -375,7 +379,7 @@ hipError_t launch_fgc_t(const Plan& pl, const Work& w, hipStream_t s, bool inver
     const int nlines = M1 * M2;
     int ncz = pow2_floor(max(1, budget / H));
     if (ncz > nlines) ncz = pow2_floor(nlines);
-    size_t shz = 2 * (size_t)H * ncz * sizeof(C2<T>);
+    size_t shz = 2 * (size_t)H * (ncz + 1) * sizeof(C2<T>);  // rows padded by one element
     const int ncomp_in = st ? 9 : 3;  // forward transforms: force (+ stresslet tensor)
     dim3 gz((nlines + ncz - 1) / ncz, ncomp_in);
     hipLaunchKernelGGL((k_fft_z<T>), gz, dim3(256), shz, s, grid, nc, nlines, H, ncz, -1, twh, twf);
