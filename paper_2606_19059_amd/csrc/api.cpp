@@ -198,11 +198,11 @@ struct CostModel {
     double fft_cell, fft0;
     double sort, sort_cell, sort0;
 };
-constexpr CostModel kCost64 = {7.488, 0.339, 0.295, 0.162, 0.086, 1.025, 0.032, 0.107, 0.061, 0.110, 0.030,
-                               0.208, 0.009, 0.043};
-constexpr CostModel kCost32 = {6.394, 0.573, 0.348, 0.140, 0.150, 0.872, 0.0, 0.002, 0.030, 0.081, 0.038,
-                               0.196, 0.011, 0.054};
-constexpr double kWaveSlots = 1536.0;  // concurrent P2P waves at which the chip is full
+constexpr CostModel kCost64 = {6.766, 0.222, 0.272, 0.152, 0.093, 0.984, 0.052, 0.110, 0.062, 0.086, 0.028,
+                               0.202, 0.009, 0.045};
+constexpr CostModel kCost32 = {5.709, 0.237, 0.315, 0.136, 0.146, 0.566, 0.059, 0.062, 0.053, 0.055, 0.037,
+                               0.232, 0.005, 0.045};
+constexpr double kWaveSlots = 2048.0;  // concurrent P2P waves at which the chip is full
 
 int p2g_blocks(const int M[3], int P)
 {
@@ -221,7 +221,12 @@ double model_ms(int mode, bool grid64, double n, const double box[3], const int 
     const double V = box[0] * box[1] * box[2];
     const double cells = (double)M[0] * M[1] * M[2];
     const double pairs = 0.5 * n * n / V * (4.0 / 3.0) * M_PI * rc * rc * rc;
-    const double waves = n / 64.0 + 0.5 * cells / ((double)B * B * B);
+    // P2P waves: one per 64-target chunk (about n/64 + tiles/2), three per chunk when the
+    // launch has few chunks (the rule of launch_p2p in p2p.hip, on its grid of tiles + n/64
+    // chunks: fewer than 40000)
+    const double tiles = cells / ((double)B * B * B);
+    const double split = (tiles + std::ceil(n / 64.0) < 40000.0) ? 3.0 : 1.0;
+    const double waves = (n / 64.0 + 0.5 * tiles) * split;
     const double np3 = n * P * P * P;
     double st[5];
     st[0] = c.sort * n * 1e-6 + c.sort_cell * cells * 1e-6 + c.sort0;
