@@ -1,5 +1,6 @@
-"""Near-field (P2P) parity over a seeded sweep of sizes, boxes, grids, splitting parameters and
-particle distributions, against the oracle's classical real-space sum (element by element).
+"""Near-field (P2P) and far-field (P2G, FFT, G2P) parity over a seeded sweep of sizes, boxes,
+grids, splitting parameters and particle distributions, against the oracle's classical
+real-space sum and spectral far field (element by element).
 
 The sizes straddle the 64-target chunks (1, 63, 64, 65, 2047, 2049 ...); the distributions put
 many particles in one tile (dense batches: the balanced drain's queue and extra rounds),
@@ -104,4 +105,26 @@ def test_p2p_sweep_stresslet_matches_oracle(case):
     err = maxrel(host(un), ref)
     bound = 1e-12 if prec == "fp64" else 2e-6
     print("P2P stresslet sweep %d: n %d %s %s: max rel err %.2e" % (case, n, kind, prec, err))
+    assert err < bound
+
+
+@pytest.mark.parametrize("case", [1, 3, 5, 8, 10, 11])
+def test_far_field_sweep_matches_oracle(case):
+    """G2P (grouped gathers: 16 targets per wavefront on FP64 grids, 32 on FP32 grids) and
+    P2G on the same sweep, against the spectral oracle's far field."""
+    from oracle import spectral as S
+
+    E = _E()
+    n, box, grid, xi, rc, kind, prec = SWEEP[case]
+    rng = np.random.default_rng(300 + case)
+    x = positions(kind, n, box, rng)
+    f = W.mean_free_forces(rng, n)
+    P = 8
+    m = 0.94 * np.sqrt(np.pi * P)
+    tol = 1e-11 if prec == "fp64" else 1e-5
+    pl = E.Plan(box, tol, xi=xi, r_c=rc, grid=grid, P=P, window_shape=m, n_max=n, precision=prec)
+    _, uf = pl.eval_parts(dev(x), dev(f))
+    err = maxrel(host(uf), S.far_field(x, f, box, grid, xi, P, m))
+    bound = 1e-11 if prec == "fp64" else 2e-5
+    print("far-field sweep %d: n %d %s %s %s: max rel err %.2e" % (case, n, kind, prec, grid, err))
     assert err < bound
