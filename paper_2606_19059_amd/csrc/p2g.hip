@@ -22,7 +22,7 @@ namespace {
 
 constexpr int kPatch = 8;     // lines per patch edge (8 x 8 = 64 lanes)
 constexpr int kWaves = 4;     // waves per block, all owning the block's lines
-constexpr int kPerWave = 16;  // particles staged per wave and round
+constexpr int kPerWave = 32;  // particles staged per wave and round
 constexpr int kChunk = kWaves * kPerWave;
 constexpr int kMaxRuns = 320; // runs per slab (window rows x z-tile segments)
 
@@ -39,8 +39,10 @@ __device__ inline void wave_lds_sync()
 // T: arithmetic and accumulation precision; TG: grid element type (the FP32 bulk mode
 // accumulates in FP64 -- the same VALU rate as FP32 without packed math -- and stores FP32).
 // A block of kWaves waves owns one (patch, x-segment): every wave keeps accumulators for
-// all 64 lines, takes every kWaves-th group of kPerWave particles of each slab, and at each
-// output step the waves' partial sums are added in a fixed order through LDS.
+// all 64 lines, takes a contiguous quarter of each slab's particles (staged kPerWave at a
+// time: 32 amortises the load and search latency of a staging round, and an even split
+// keeps the waves of a block equally busy), and at each output step the waves' partial
+// sums are added in a fixed order through LDS.
 template <typename T, typename TG, int P>
 __global__ __launch_bounds__(kWaves * 64) void k_p2g_sweep(const typename RecView<T>::Rec* __restrict__ rec,
                                                            const int* __restrict__ start, Geometry g,
@@ -109,12 +111,15 @@ __global__ __launch_bounds__(kWaves * 64) void k_p2g_sweep(const typename RecVie
         __syncthreads();
         const int total = run_pre[R];
 
-        for (int base = 0; base < total; base += kChunk) {
-            // each wave stages its own kPerWave particles of the chunk
-            const int q0 = wid * kPerWave;
-            const int cnt = max(0, min(kPerWave, total - base - q0));
+        // the slab's particles are split evenly over the waves; each wave stages and spreads
+        // its share in rounds of kPerWave
+        const int share = (total + kWaves - 1) / kWaves;
+        const int wend = min(total, (wid + 1) * share);
+        const int q0 = wid * kPerWave;
+        for (int base = wid * share; base < wend; base += kPerWave) {
+            const int cnt = min(kPerWave, wend - base);
             if (lane < cnt) {
-                const int flat = base + q0 + lane;
+                const int flat = base + lane;
                 int lo = 0, hi = R;
                 while (hi - lo > 1) {
                     const int mid = (lo + hi) >> 1;
@@ -144,8 +149,8 @@ __global__ __launch_bounds__(kWaves * 64) void k_p2g_sweep(const typename RecVie
             wave_lds_sync();
             if (!wa.kb) {
                 // Gaussian: one lane per (particle, axis), two exponentials and P products
-                if (lane < 3 * cnt) {
-                    const int qq = q0 + lane / 3, d = lane % 3;
+                for (int li = lane; li < 3 * cnt; li += kWave) {
+                    const int qq = q0 + li / 3, d = li % 3;
                     T wv[P];
                     window_weights<T, P>(st[qq][d], wa, wv);
 #pragma unroll
