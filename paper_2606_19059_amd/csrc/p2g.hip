@@ -10,10 +10,12 @@
 // final value, and the register window shifts by one.  Every grid point is written by
 // exactly one lane, in a fixed particle order: deterministic, no atomics, no zero-fill.
 // The particles of a slab that can reach the patch (a (8+P-1)^2 window of cells) are
-// contiguous runs of the cell-sorted arrays; they are staged in LDS with their 3 x P
-// separable 1D weights (computed once per particle and wave), then every lane reads them
-// by broadcast.  The x direction is exact (no wasted work); in y and z a lane whose line is
-// outside the particle's P x P footprint multiplies by zero.
+// contiguous runs of the cell-sorted arrays; they are staged in LDS with their P x weights
+// and, per line of the patch, the y weight and the z weight times f (zero where the line is
+// outside the particle's P x P footprint), so a lane's factor for a particle is
+// w_y[ly] * (w_z f)[lz], read without any dependent index arithmetic.  The x direction is
+// exact (no wasted work); in y and z a lane whose line is outside the footprint multiplies
+// by zero.
 #include "window.h"
 
 namespace ewald {
@@ -53,7 +55,9 @@ __global__ __launch_bounds__(kWaves * 64) void k_p2g_sweep(const typename RecVie
     constexpr int W = kPatch + P - 1;
     __shared__ int run_start[kMaxRuns];
     __shared__ int run_pre[kMaxRuns + 1];
-    __shared__ T sw[kChunk][3][P];
+    __shared__ T swx[kChunk][P];             // x weights of the staged particles
+    __shared__ T swy[kChunk][kPatch];        // y weight of each patch line (0 off the footprint)
+    __shared__ T swz[kChunk][3][kPatch];     // z weight of each patch line times the 3 sources
     __shared__ T sf[kChunk][3];
     __shared__ T st[kChunk][3];  // in-cell fractions (Kaiser-Bessel weights are computed from them)
     __shared__ int soff[kChunk];
@@ -69,6 +73,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_p2g_sweep(const typename RecVie
     const int ly = lane >> 3, lz = lane & 7;
     const int B = g.B;
 
+    const T e2 = exp((T)-2 * wa.beta);  // ratio of consecutive Gaussian recurrence factors
     T acc[P][3];
 #pragma unroll
     for (int k = 0; k < P; ++k) acc[k][0] = acc[k][1] = acc[k][2] = (T)0;
@@ -109,7 +114,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_p2g_sweep(const typename RecVie
             if (lane == 0) run_pre[0] = 0;
         }
         __syncthreads();
-        const int total = run_pre[R];
+        const int total = __builtin_amdgcn_readfirstlane(run_pre[R]);
 
         // the slab's particles are split evenly over the waves; each wave stages and spreads
         // its share in rounds of kPerWave
@@ -148,34 +153,76 @@ __global__ __launch_bounds__(kWaves * 64) void k_p2g_sweep(const typename RecVie
             }
             wave_lds_sync();
             if (!wa.kb) {
-                // Gaussian: one lane per (particle, axis), two exponentials and P products
-                for (int li = lane; li < 3 * cnt; li += kWave) {
-                    const int qq = q0 + li / 3, d = li % 3;
+                // Gaussian x weights: one lane per particle, two exponentials and P products
+                if (lane < cnt) {
                     T wv[P];
-                    window_weights<T, P>(st[qq][d], wa, wv);
+                    window_weights<T, P>(st[q0 + lane][0], wa, wv);
 #pragma unroll
-                    for (int k = 0; k < P; ++k) sw[qq][d][k] = wv[k];
+                    for (int k = 0; k < P; ++k) swx[q0 + lane][k] = wv[k];
+                }
+                // y and z weights of the patch's lines, one lane per (particle, axis): line l is at
+                // stencil offset j = l - o and distance u0 + l from the particle, and the Gaussian
+                // obeys w(u + 1) = w(u) exp(-beta (2u + 1)): two exponentials and 2 x 8 products
+                for (int li = lane; li < 2 * cnt; li += kWave) {
+                    const int qq = q0 + (li >> 1);
+                    const bool isy = (li & 1) == 0;
+                    const int off = soff[qq];
+                    const int o = (isy ? (off & 255) : (off >> 8)) - P;  // stencil anchor - patch origin
+                    const T t = st[qq][isy ? 1 : 2];
+                    const T u0 = (T)(-o - (P / 2 - 1)) - t;
+                    T w = exp(-wa.beta * u0 * u0);
+                    T r = exp(-wa.beta * ((T)2 * u0 + (T)1));
+                    T wl[kPatch];
+#pragma unroll
+                    for (int l = 0; l < kPatch; ++l) {
+                        const int j = l - o;
+                        const bool in = (unsigned)j < (unsigned)P && !(j == P - 1 && t == (T)0);
+                        wl[l] = in ? w : (T)0;
+                        w *= r;
+                        r *= e2;
+                    }
+                    if (isy) {
+#pragma unroll
+                        for (int l = 0; l < kPatch; ++l) swy[qq][l] = wl[l];
+                    } else {
+                        const T f0 = sf[qq][0], f1 = sf[qq][1], f2 = sf[qq][2];
+#pragma unroll
+                        for (int l = 0; l < kPatch; ++l) {
+                            swz[qq][0][l] = wl[l] * f0;
+                            swz[qq][1][l] = wl[l] * f1;
+                            swz[qq][2][l] = wl[l] * f2;
+                        }
+                    }
                 }
             } else {
                 // Kaiser-Bessel: one polynomial per weight, spread over all lanes of the wave
-                for (int k = lane; k < cnt * 3 * P; k += kWave) {
-                    const int qq = q0 + k / (3 * P), d = (k / P) % 3, j = k % P;
-                    sw[qq][d][j] = window_weight_one<T, P>(j, st[qq][d], wa);
+                for (int k = lane; k < cnt * P; k += kWave) {
+                    const int qq = q0 + k / P, j = k % P;
+                    swx[qq][j] = window_weight_one<T, P>(j, st[qq][0], wa);
+                }
+                for (int k = lane; k < cnt * 2 * kPatch; k += kWave) {
+                    const int qq = q0 + k / (2 * kPatch), l = k % kPatch;
+                    const bool isy = (k / kPatch) % 2 == 0;
+                    const int off = soff[qq];
+                    const int j = l + P - (isy ? (off & 255) : (off >> 8));  // stencil offset of line l
+                    T wv = (T)0;
+                    if ((unsigned)j < (unsigned)P) wv = window_weight_one<T, P>(j, st[qq][isy ? 1 : 2], wa);
+                    if (isy) {
+                        swy[qq][l] = wv;
+                    } else {
+                        swz[qq][0][l] = wv * sf[qq][0];
+                        swz[qq][1][l] = wv * sf[qq][1];
+                        swz[qq][2][l] = wv * sf[qq][2];
+                    }
                 }
             }
             wave_lds_sync();
             for (int q = q0; q < q0 + cnt; ++q) {
-                const int off = soff[q];
-                const int ky = ly - ((off & 255) - P);
-                const int kz = lz - ((off >> 8) - P);
-                const T wy = sw[q][1][min(max(ky, 0), P - 1)];
-                const T wz = sw[q][2][min(max(kz, 0), P - 1)];
-                const bool in = (unsigned)ky < (unsigned)P && (unsigned)kz < (unsigned)P;
-                const T wyz = in ? wy * wz : (T)0;
-                const T g0 = wyz * sf[q][0], g1 = wyz * sf[q][1], g2 = wyz * sf[q][2];
+                const T wy = swy[q][ly];
+                const T g0 = wy * swz[q][0][lz], g1 = wy * swz[q][1][lz], g2 = wy * swz[q][2][lz];
 #pragma unroll
                 for (int k = 0; k < P; ++k) {
-                    const T wx = sw[q][0][k];
+                    const T wx = swx[q][k];
                     acc[k][0] += wx * g0;
                     acc[k][1] += wx * g1;
                     acc[k][2] += wx * g2;
