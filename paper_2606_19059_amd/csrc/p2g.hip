@@ -217,6 +217,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_p2g_sweep(const typename RecVie
                 }
             }
             wave_lds_sync();
+#pragma unroll (P <= 12 ? 2 : 1)
             for (int q = q0; q < q0 + cnt; ++q) {
                 const T wy = swy[q][ly];
                 const T g0 = wy * swz[q][0][lz], g1 = wy * swz[q][1][lz], g2 = wy * swz[q][2][lz];

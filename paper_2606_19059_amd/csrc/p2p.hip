@@ -116,25 +116,30 @@ __device__ inline double exp_neg_fast(double y, const PairArgs& a)
     return ldexp(p, (int)n);
 }
 
-// Coefficients of G^N(r) f = a1 f + b (r.f) r for 0 < r^2 < r_c^2 (FP64)
-// 1/sqrt(r2) for finite r2 > 0: hardware estimate, then one third-order correction
-// y (1 + e/2 + 3e^2/8), e = 1 - r2 y^2 (no special-value handling)
+// 1/sqrt(r2) for finite r2 > 0: hardware estimate y (error bound 2^29 ulp, ~2^-23
+// relative), then with e = 1 - r2 y^2 one third-order correction y (1 + e/2 + 3e^2/8) (full
+// FP64), or for Fast one Newton step y (1 + e/2) (relative error ~ 3e^2/8, below 1e-13).
+// No special values.
+template <bool Fast>
 __device__ inline double rsqrt_pos(double r2)
 {
     const double y = __builtin_amdgcn_rsq(r2);
     const double e = fma(-r2 * y, y, 1.0);
+    if (Fast) return fma(y * e, 0.5, y);
     return fma(y * e, fma(0.375, e, 0.5), y);
 }
 
+// Coefficients of G^N(r) f = a1 f + b (r.f) r for 0 < r^2 < r_c^2 (FP64):
+// a1 = C/r - (4 xi/sqrt(pi)) e, b = C/r^3
 template <bool Fast>
 __device__ inline void coef64(double r2, const PairArgs& a, double& a1, double& b)
 {
-    const double rinv = rsqrt_pos(r2);
+    const double rinv = rsqrt_pos<Fast>(r2);
     const double x = a.xi * r2 * rinv;
     const double e = Fast ? exp_neg_fast(a.xi2 * r2, a) : exp(-a.xi2 * r2);
-    const double C = e * screen_q64<Fast>(x, a);
-    a1 = fma(C, rinv, -a.four_xi_over_sqrtpi * e);
-    b = C * rinv * (rinv * rinv);
+    const double Cr = e * screen_q64<Fast>(x, a) * rinv;
+    a1 = fma(-a.four_xi_over_sqrtpi, e, Cr);
+    b = Cr * (rinv * rinv);
 }
 
 // FP32 versions (FP32 bulk mode): hardware reciprocal, rsqrt (+ one Newton step) and exp2,
@@ -594,11 +599,59 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
             qx += __popcll(bw);
         }
         __syncthreads();
-        // 3. `rounds` rounds, one pair per lane: the lane's own target while it has pairs
-        //    (target side summed in registers), then queue entries in order (target side by
-        //    LDS atomics); the source side goes to the batch's source accumulators
+        // 3. `rounds` rounds of one pair per lane; a lane's own target's side is summed in
+        //    registers, the source side goes to the batch's source accumulators.
+        // The pair (target tt at position p with force tf, ring slot): c = G^N(r) f_source for
+        // the target, d = G^N(-r) f_target for the source (r = p - x_source)
+        auto pair = [&](double p0, double p1, double p2, TF tf0, TF tf1, TF tf2, int tt, int slot, TF& c0,
+                        TF& c1, TF& c2, TF& d0, TF& d1, TF& d2) {
+            const double rx = p0 - ring[0][slot];
+            const double ry = p1 - ring[1][slot];
+            const double rz = p2 - ring[2][slot];
+            const double r2 = rx * rx + ry * ry + rz * rz;
+            TF a1, b;
+            if constexpr (ST) {
+                TF al, be;
+                CoefSt<TF, Fast>::eval(r2, a, a1, b, al, be);
+                apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, ringf[0][slot], ringf[1][slot], ringf[2][slot], c0, c1, c2);
+                apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, tf0, tf1, tf2, d0, d1, d2);
+                TF ss[6], st[6];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    ss[c] = rings[c][slot];
+                    st[c] = -tgts[c][tt];  // T^N(-r) = -T^N(r)
+                }
+                apply_st<TF>(al, be, (TF)rx, (TF)ry, (TF)rz, ss, c0, c1, c2);
+                apply_st<TF>(al, be, (TF)rx, (TF)ry, (TF)rz, st, d0, d1, d2);
+            } else {
+                Coef<TF, Fast>::eval(r2, a, a1, b);
+                apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, ringf[0][slot], ringf[1][slot], ringf[2][slot], c0, c1, c2);
+                apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, tf0, tf1, tf2, d0, d1, d2);
+            }
+        };
+        const int rq = lane / (kWave / kCp);
+        // 3a. rounds in which every lane still takes a pair of its own target (about a third
+        //     at uniform density): no queue, no ballot, and the target's position and force
+        //     come from registers
+        const int own_all = uniform_i((int)wave_min((double)own_n));
+        const TF mf0 = (TF)me.f[0], mf1 = (TF)me.f[1], mf2 = (TF)me.f[2];
+        for (int r = 0; r < own_all; ++r) {
+            const int sl = (__ffs(rm) - 1 + rot) & (kB - 1);
+            rm &= rm - 1;
+            const int slot = (rhead + sl) & (kSymRing - 1);
+            TF c0, c1, c2, d0, d1, d2;
+            pair(tx[0], tx[1], tx[2], mf0, mf1, mf2, lane, slot, c0, c1, c2, d0, d1, d2);
+            oacc[0] += (double)c0;
+            oacc[1] += (double)c1;
+            oacc[2] += (double)c2;
+            atomicAdd(&racc[0][rq][sl], (double)d0);
+            atomicAdd(&racc[1][rq][sl], (double)d1);
+            atomicAdd(&racc[2][rq][sl], (double)d2);
+        }
+        // 3b. the remaining rounds, one pair per lane: the lane's own target while it has
+        //     pairs, then queue entries in order (target side by LDS atomics)
         int qb = 0;
-        for (int r = 0; r < rounds; ++r) {
+        for (int r = own_all; r < rounds; ++r) {
             // branch-free round: every lane reads a queue entry (in range, used only by
             // donated lanes) and its target's data from LDS (its own target for own lanes)
             const bool own = r < own_n;
@@ -612,29 +665,9 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
             const int tt = own ? lane : (e & (kWave - 1));
             const int sl = own ? ((pb + rot) & (kB - 1)) : ((e >> 6) & (kB - 1));
             const int slot = (rhead + sl) & (kSymRing - 1);
-            const double rx = tgt[0][tt] - ring[0][slot];
-            const double ry = tgt[1][tt] - ring[1][slot];
-            const double rz = tgt[2][tt] - ring[2][slot];
-            const double r2 = rx * rx + ry * ry + rz * rz;
-            TF a1, b, c0, c1, c2, d0, d1, d2;
-            if constexpr (ST) {
-                TF al, be;
-                CoefSt<TF, Fast>::eval(r2, a, a1, b, al, be);
-                apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, ringf[0][slot], ringf[1][slot], ringf[2][slot], c0, c1, c2);
-                apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, tgtf[0][tt], tgtf[1][tt], tgtf[2][tt], d0, d1, d2);
-                TF ss[6], st[6];
-#pragma unroll
-                for (int c = 0; c < 6; ++c) {
-                    ss[c] = rings[c][slot];
-                    st[c] = -tgts[c][tt];  // T^N(-r) = -T^N(r)
-                }
-                apply_st<TF>(al, be, (TF)rx, (TF)ry, (TF)rz, ss, c0, c1, c2);
-                apply_st<TF>(al, be, (TF)rx, (TF)ry, (TF)rz, st, d0, d1, d2);
-            } else {
-                Coef<TF, Fast>::eval(r2, a, a1, b);
-                apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, ringf[0][slot], ringf[1][slot], ringf[2][slot], c0, c1, c2);
-                apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, tgtf[0][tt], tgtf[1][tt], tgtf[2][tt], d0, d1, d2);
-            }
+            TF c0, c1, c2, d0, d1, d2;
+            pair(tgt[0][tt], tgt[1][tt], tgt[2][tt], tgtf[0][tt], tgtf[1][tt], tgtf[2][tt], tt, slot, c0, c1, c2,
+                 d0, d1, d2);
             if (own) {
                 oacc[0] += (double)c0;
                 oacc[1] += (double)c1;
@@ -646,7 +679,6 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
                 atomicAdd(&acc[2][tt], (double)c2);
             }
             if (own || don) {
-                const int rq = lane / (kWave / kCp);
                 atomicAdd(&racc[0][rq][sl], (double)d0);
                 atomicAdd(&racc[1][rq][sl], (double)d1);
                 atomicAdd(&racc[2][rq][sl], (double)d2);
