@@ -2,9 +2,12 @@
 (`k_p2p_sym`, Stokeslet-only form): per batch of 32 ring entries a lane keeps up to
 R = ceil(Q / 64) pairs of its own target, taken in an order rotated by lane mod 32 (lowest
 rotated bit first), and queues the rest (highest rotated bits first); lanes with fewer
-than R pairs take queue entries in order in their spare rounds.  The model checks that
-every accepted (target, entry) pair is evaluated exactly once within R rounds and that
-the queue never exceeds its 512 entries, on random, sparse and adversarial masks."""
+than R pairs take queue entries in order in their spare rounds.  The first min over lanes
+of the own-pair counts are rounds in which every lane takes its own pair; the kernel runs
+them as a separate loop (no ballot, no queue) and starts the general rounds after them.
+The model checks that every accepted (target, entry) pair is evaluated exactly once within
+R rounds, that every lane has a pair of its own in each of the separate loop's rounds, and
+that the queue never exceeds its 512 entries, on random, sparse and adversarial masks."""
 import numpy as np
 import pytest
 
@@ -31,7 +34,14 @@ def schedule(acc):
                 queue.append((l, (pb + rot[l]) & (K - 1)))
                 ex[l] -= 1
     done, qb = [], 0
-    for r in range(rounds):
+    own_all = min(own_n)
+    for r in range(own_all):                # every lane pops its own lowest rotated bit
+        for l in range(LANES):
+            assert rm[l] != 0
+            pb = (rm[l] & -rm[l]).bit_length() - 1
+            rm[l] &= rm[l] - 1
+            done.append((l, (pb + rot[l]) & (K - 1)))
+    for r in range(own_all, rounds):
         rank = 0
         for l in range(LANES):
             if r < own_n[l]:
@@ -44,7 +54,7 @@ def schedule(acc):
                 if q < len(queue):
                     done.append(queue[q])
         qb += rank
-    return done, len(queue), rounds
+    return done, len(queue), rounds, own_all
 
 
 def masks(seed):
@@ -68,7 +78,7 @@ def masks(seed):
 @pytest.mark.parametrize("seed", [0, 1])
 def test_every_pair_once_and_queue_bound(seed):
     for acc in masks(seed):
-        done, qlen, rounds = schedule(acc)
+        done, qlen, rounds, _ = schedule(acc)
         want = sorted((l, j) for l in range(LANES) for j in range(acc.shape[1]) if acc[l, j])
         assert sorted(done) == want
         assert len(done) <= rounds * LANES
@@ -78,5 +88,21 @@ def test_every_pair_once_and_queue_bound(seed):
 def test_queue_worst_case_is_reached():
     acc = np.zeros((LANES, K), bool)
     acc[:32] = True
-    _, qlen, rounds = schedule(acc)
-    assert (qlen, rounds) == (512, 16)
+    _, qlen, rounds, own_all = schedule(acc)
+    assert (qlen, rounds, own_all) == (512, 16, 0)
+
+
+def test_dense_batches_run_mostly_in_the_all_own_loop():
+    # every lane accepts 24..32 of the 32 entries (a target deep inside the cutoff sphere of
+    # the batch): R <= 32 and every lane holds at least 24 pairs, so the separate loop takes
+    # min(R, 24) rounds and the general rounds only balance the remainder
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        k = rng.integers(24, K + 1, LANES)
+        acc = np.zeros((LANES, K), bool)
+        for l in range(LANES):
+            acc[l, rng.choice(K, k[l], replace=False)] = True
+        done, qlen, rounds, own_all = schedule(acc)
+        assert own_all == min(rounds, int(k.min()))
+        assert sorted(done) == sorted((l, j) for l in range(LANES) for j in range(K) if acc[l, j])
+        assert qlen <= QUEUE
