@@ -308,6 +308,8 @@ int64_t layout_work(const Plan& pl, int64_t n, char* base, Work* w)
     o->u_near = (double*)take(8 * 3 * nn);
     o->srec = pl.stresslet ? (double*)take(8 * 6 * nn) : nullptr;
     o->grid = (void*)take((int64_t)real * (pl.stresslet ? 9 : 3) * g.ncells);
+    const int64_t nh = p2g_halo_elems(pl);
+    o->p2g_halo = nh > 0 ? (double*)take(8 * nh) : nullptr;
     o->bytes = off;
     return off;
 }

@@ -106,10 +106,13 @@ struct Work {
                      // (stresslet plans only)
     void* grid;      // 3 (9 for stresslet plans) x ncells reals (double or float), then the
                      // in-place half spectrum
+    double* p2g_halo;  // P2G's partial sums next to its x-segment boundaries (p2g_halo_elems)
     int64_t bytes;
 };
 
 int64_t layout_work(const Plan& pl, int64_t n, char* base, Work* w);
+// doubles of P2G's segment-boundary buffer for this plan (0: the sweep uses no halo)
+int64_t p2g_halo_elems(const Plan& pl);
 
 // Launchers (all enqueue on `s`, return hipSuccess or the launch error).
 hipError_t launch_sort(const Plan& pl, const Work& w, int n, const double* x, const double* f,

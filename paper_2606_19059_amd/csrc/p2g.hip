@@ -16,6 +16,8 @@
 // w_y[ly] * (w_z f)[lz], read without any dependent index arithmetic.  The x direction is
 // exact (no wasted work); in y and z a lane whose line is outside the footprint multiplies
 // by zero.
+#include <type_traits>
+
 #include "window.h"
 
 namespace ewald {
@@ -50,7 +52,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_p2g_sweep(const typename RecVie
                                                            const int* __restrict__ start, Geometry g,
                                                            WinArgs<T> wa, int seg, int npy, int npz,
                                                            const double* __restrict__ sv, int sv_off,
-                                                           TG* __restrict__ grid)
+                                                           TG* __restrict__ grid, double* __restrict__ halo)
 {
     constexpr int W = kPatch + P - 1;
     __shared__ int run_start[kMaxRuns];
@@ -84,7 +86,40 @@ __global__ __launch_bounds__(kWaves * 64) void k_p2g_sweep(const typename RecVie
     const int R = W * nzs;
     const int64_t nc = g.ncells;
 
-    for (int cxu = x0 - P / 2; cxu <= x1 + P / 2 - 2; ++cxu) {
+    // Output steps: the partial sums of the waves are added in a fixed order through LDS and
+    // the sum of wave 0 goes to dst[0], dst[cs], dst[2 cs] (the three components).
+    auto output = [&](T a0, T a1, T a2, auto* dst, int64_t cs) {
+        if (wid > 0) {
+            red[wid - 1][0][lane] = a0;
+            red[wid - 1][1][lane] = a1;
+            red[wid - 1][2][lane] = a2;
+        }
+        __syncthreads();
+        if (wid == 0) {
+#pragma unroll
+            for (int k = 0; k < kWaves - 1; ++k) {
+                a0 += red[k][0][lane];
+                a1 += red[k][1][lane];
+                a2 += red[k][2][lane];
+            }
+            using D = typename std::remove_pointer<decltype(dst)>::type;
+            dst[0] = (D)a0;
+            dst[cs] = (D)a1;
+            dst[2 * cs] = (D)a2;
+        }
+    };
+    // With halo == nullptr the segment's sweep starts P - 1 slabs early (a warm-up that makes its
+    // first points complete).  With a halo buffer it sweeps only its own slabs [x0, x1): its first
+    // and last P - 1 points are then partial, and go to the halo's head and tail planes of this
+    // segment (head[s][k] and tail[s][k] hold the point x0 - P/2 + 1 + k and x1 - P/2 + 1 + k);
+    // k_p2g_halo_sum adds tail[s - 1] to head[s] into the grid.
+    const int64_t m23 = (int64_t)M2 * M3;
+    const int64_t line = (int64_t)(y0 + ly) * M3 + (z0 + lz);
+    const int hk = P - 1;
+    double* head = halo ? halo + (int64_t)sx * hk * 3 * m23 + line : nullptr;
+    double* tail = halo ? halo + ((int64_t)gridDim.x / (npy * npz) + sx) * hk * 3 * m23 + line : nullptr;
+    const int cbeg = halo ? x0 : x0 - P / 2, cend = halo ? x1 - 1 : x1 + P / 2 - 2;
+    for (int cxu = cbeg; cxu <= cend; ++cxu) {
         const int cx = wrapi(cxu, M1);
         // runs of this slab: one per (window row, z-tile segment); wave 0 builds the table
         int carry = 0;
@@ -233,27 +268,10 @@ __global__ __launch_bounds__(kWaves * 64) void k_p2g_sweep(const typename RecVie
         }
 
         const int xo = cxu - P / 2 + 1;
-        if (xo >= x0) {
-            if (wid > 0) {
-                red[wid - 1][0][lane] = acc[0][0];
-                red[wid - 1][1][lane] = acc[0][1];
-                red[wid - 1][2][lane] = acc[0][2];
-            }
-            __syncthreads();
-            if (wid == 0) {
-                T v0 = acc[0][0], v1 = acc[0][1], v2 = acc[0][2];
-#pragma unroll
-                for (int k = 0; k < kWaves - 1; ++k) {
-                    v0 += red[k][0][lane];
-                    v1 += red[k][1][lane];
-                    v2 += red[k][2][lane];
-                }
-                const int64_t idx = ((int64_t)xo * M2 + (y0 + ly)) * M3 + (z0 + lz);
-                grid[idx] = (TG)v0;
-                grid[nc + idx] = (TG)v1;
-                grid[2 * nc + idx] = (TG)v2;
-            }
-        }
+        if (halo && xo < x0 + P / 2)
+            output(acc[0][0], acc[0][1], acc[0][2], head + (int64_t)(xo - (x0 - P / 2 + 1)) * 3 * m23, m23);
+        else if (xo >= x0)
+            output(acc[0][0], acc[0][1], acc[0][2], grid + (int64_t)xo * m23 + line, nc);
 #pragma unroll
         for (int k = 0; k + 1 < P; ++k) {
             acc[k][0] = acc[k + 1][0];
@@ -263,26 +281,71 @@ __global__ __launch_bounds__(kWaves * 64) void k_p2g_sweep(const typename RecVie
         acc[P - 1][0] = acc[P - 1][1] = acc[P - 1][2] = (T)0;
         __syncthreads();
     }
+    if (halo) {
+#pragma unroll
+        for (int k = 0; k < P - 1; ++k) {
+            output(acc[k][0], acc[k][1], acc[k][2], tail + (int64_t)k * 3 * m23, m23);
+            __syncthreads();
+        }
+    }
 }
 
+// The points next to the segment boundaries: grid(x0(s) - P/2 + 1 + k) = head[s][k] + tail[s-1][k]
+// (periodic in s), for k < P - 1, every line and component; head and tail planes are laid out
+// [segment][k][component][line].
+template <typename TG>
+__global__ __launch_bounds__(256) void k_p2g_halo_sum(const double* __restrict__ halo, int nseg, int seg, int P,
+                                                      Geometry g, TG* __restrict__ grid)
+{
+    const int64_t m23 = (int64_t)g.M[1] * g.M[2];
+    const int64_t planes = (int64_t)nseg * (P - 1) * 3;
+    const int64_t total = planes * m23;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t yz = i % m23, pl = i / m23;
+        const int c = (int)(pl % 3), sk = (int)(pl / 3);
+        const int k = sk % (P - 1), sg = sk / (P - 1);
+        const int sp = (sg + nseg - 1) % nseg;
+        const double v = halo[i] + halo[total + ((int64_t)(sp * (P - 1) + k) * 3 + c) * m23 + yz];
+        const int x = wrapi(sg * seg - P / 2 + 1 + k, g.M[0]);
+        grid[(int64_t)c * g.ncells + (int64_t)x * m23 + yz] = (TG)v;
+    }
+}
+
+
+// x-segment length of the sweep: long enough that the per-segment cost (the halo planes, or
+// the (P-1)-slab warm-up without them) is small, short enough to give the chip several waves
+// per SIMD
+int segment_length(const Geometry& g, int P)
+{
+    const int npy = g.M[1] / kPatch, npz = g.M[2] / kPatch;
+    int seg = g.M[0];
+    while (seg > 4 * P && (int64_t)(g.M[0] / seg) * npy * npz < 1024) seg >>= 1;
+    return seg;
+}
 
 template <typename TG, int P>
 hipError_t launch_p2g_t(const Plan& pl, const Work& w, hipStream_t s, bool st)
 {
     const Geometry& g = pl.g;
     const int npy = g.M[1] / kPatch, npz = g.M[2] / kPatch;
-    // x-segment length: long enough that the (P-1)-slab warm-up is a small overhead,
-    // short enough to give the chip several waves per SIMD
-    int seg = g.M[0];
-    while (seg > 4 * P && (int64_t)(g.M[0] / seg) * npy * npz < 1024) seg >>= 1;
-    const int nseg = (g.M[0] + seg - 1) / seg;
+    const int seg = segment_length(g, P);
+    const int nseg = g.M[0] / seg;
     const int blocks = nseg * npy * npz;
+    // the halo scheme needs every boundary point to lie in exactly two segments
+    double* halo = seg >= P ? w.p2g_halo : nullptr;
+    const int64_t halo_n = (int64_t)nseg * (P - 1) * 3 * g.M[1] * g.M[2];
+    const int fix_blocks = (int)std::min<int64_t>((halo_n + 255) / 256, 4096);
     // force (3 components); with stresslet sources also the 6 tensor components, three per sweep
     const int passes = st ? 3 : 1;
-    for (int ps = 0; ps < passes; ++ps)
+    for (int ps = 0; ps < passes; ++ps) {
+        TG* grid = (TG*)w.grid + (int64_t)3 * ps * g.ncells;
         hipLaunchKernelGGL((k_p2g_sweep<double, TG, P>), dim3(blocks), dim3(kWaves * kWave), 0, s,
                            (const Rec64*)w.rec, w.start, g, make_win_args<double>(pl), seg, npy, npz,
-                           ps == 0 ? nullptr : w.srec, 3 * (ps - 1), (TG*)w.grid + (int64_t)3 * ps * g.ncells);
+                           ps == 0 ? nullptr : w.srec, 3 * (ps - 1), grid, halo);
+        if (halo)
+            hipLaunchKernelGGL((k_p2g_halo_sum<TG>), dim3(fix_blocks), dim3(256), 0, s, (const double*)halo, nseg,
+                               seg, P, g, grid);
+    }
     return hipGetLastError();
 }
 
@@ -304,6 +367,13 @@ hipError_t launch_p2g_p(const Plan& pl, const Work& w, hipStream_t s, bool st)
 }  // namespace
 
 int p2g_max_runs() { return kMaxRuns; }
+
+int64_t p2g_halo_elems(const Plan& pl)
+{
+    const int seg = segment_length(pl.g, pl.P);
+    if (seg < pl.P) return 0;
+    return 2 * (int64_t)(pl.g.M[0] / seg) * (pl.P - 1) * 3 * pl.g.M[1] * pl.g.M[2];
+}
 
 hipError_t launch_p2g(const Plan& pl, const Work& w, int n, hipStream_t s, bool st)
 {

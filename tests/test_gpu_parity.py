@@ -50,6 +50,10 @@ CASES = {
     "grid8_P8": ((1.0, 1.0, 1.0), (8, 8, 8), 3.0, 0.45, 8, 4.6),
     "long_P6": ((1.0, 1.0, 4.0), (16, 16, 64), 6.0, 0.5, 6, 4.1),
     "cube16_P16": ((1.0, 1.0, 1.0), (16, 16, 16), 6.0, 0.45, 16, 6.6),
+    # grids whose P2G sweep is cut into x-segments (2 of 32 planes, 8 of 16 planes): the
+    # points next to the segment boundaries are summed from two segments' halo planes
+    "cube64_P8": ((1.0, 1.0, 1.0), (64, 64, 64), 20.0, 0.2, 8, 4.8),
+    "xlong_P4": ((4.0, 0.5, 0.5), (128, 16, 16), 12.0, 0.2, 4, 3.0),
 }
 
 
@@ -68,7 +72,8 @@ def test_tiny_eval_runs():
 
 
 @pytest.mark.parametrize("name,n", [("cube32_P8", 2000), ("aniso_P12", 1531), ("grid8_P8", 300),
-                                    ("long_P6", 2049), ("cube16_P16", 700)])
+                                    ("long_P6", 2049), ("cube16_P16", 700), ("cube64_P8", 3000),
+                                    ("xlong_P4", 2500)])
 def test_p2g_grid_matches_oracle(name, n):
     E = _E()
     box, grid, xi, rc, P, m = CASES[name]
@@ -79,7 +84,7 @@ def test_p2g_grid_matches_oracle(name, n):
     assert maxrel(g, ref) < 1e-12
 
 
-@pytest.mark.parametrize("name,n", [("cube32_P8", 2000), ("aniso_P12", 1531), ("long_P6", 900)])
+@pytest.mark.parametrize("name,n", [("cube32_P8", 2000), ("aniso_P12", 1531), ("long_P6", 900), ("xlong_P4", 1200)])
 def test_far_grid_matches_oracle(name, n):
     E = _E()
     box, grid, xi, rc, P, m = CASES[name]
