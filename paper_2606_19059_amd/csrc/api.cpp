@@ -207,9 +207,7 @@ constexpr double kWaveSlots = 2048.0;  // concurrent P2P waves at which the chip
 int p2g_blocks(const int M[3], int P)
 {
     const int npy = std::max(1, M[1] / 8), npz = std::max(1, M[2] / 8);
-    int seg = M[0];
-    while (seg > 4 * P && (int64_t)(M[0] / seg) * npy * npz < 1024) seg >>= 1;
-    return ((M[0] + seg - 1) / seg) * npy * npz;
+    return (M[0] / p2g_segment_length(M, P)) * npy * npz;
 }
 
 // predicted ms per stage (sort, P2P, P2G, FFT+CNV+IFFT, G2P) for n particles

@@ -113,6 +113,8 @@ struct Work {
 int64_t layout_work(const Plan& pl, int64_t n, char* base, Work* w);
 // doubles of P2G's segment-boundary buffer for this plan (0: the sweep uses no halo)
 int64_t p2g_halo_elems(const Plan& pl);
+// length of the x-segments of P2G's sweep (a power of two dividing M[0])
+int p2g_segment_length(const int M[3], int P);
 
 // Launchers (all enqueue on `s`, return hipSuccess or the launch error).
 hipError_t launch_sort(const Plan& pl, const Work& w, int n, const double* x, const double* f,
