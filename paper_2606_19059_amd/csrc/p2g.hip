@@ -6,9 +6,11 @@
 // [x0, x1), and sweeps the particle slabs of constant cell-x in increasing order.  Each
 // lane keeps P x-accumulators per component in registers: a particle in cell-x c adds
 // w_x[k] * w_y * w_z * f to the lane's points x = c - P/2 + 1 + k; after slab c has been
-// processed the point x = c - P/2 + 1 receives nothing more, so it is written once, to its
-// final value, and the register window shifts by one.  Every grid point is written by
-// exactly one lane, in a fixed particle order: deterministic, no atomics, no zero-fill.
+// processed the point x = c - P/2 + 1 receives nothing more from the segment, so it is
+// written once and the register window shifts by one.  The first and last P - 1 points of a
+// segment also receive from the neighbouring segment: both segments write their partial
+// sums to halo planes, which k_p2g_halo_sum adds into the grid.  Every grid point has one
+// writer and a fixed summation order: deterministic, no atomics, no zero-fill.
 // The particles of a slab that can reach the patch (a (8+P-1)^2 window of cells) are
 // contiguous runs of the cell-sorted arrays; they are staged in LDS with their P x weights
 // and, per line of the patch, the y weight and the z weight times f (zero where the line is
