@@ -190,12 +190,20 @@ __global__ __launch_bounds__(kWaves * 64) void k_p2g_sweep(const typename RecVie
             }
             wave_lds_sync();
             if (!wa.kb) {
-                // Gaussian x weights: one lane per particle, two exponentials and P products
-                if (lane < cnt) {
-                    T wv[P];
-                    window_weights<T, P>(st[q0 + lane][0], wa, wv);
+                // Gaussian x weights: two lanes per particle, P/2 consecutive weights each by the
+                // same recurrence (two exponentials per lane)
+                for (int li = lane; li < 2 * cnt; li += kWave) {
+                    const int qq = q0 + (li >> 1), j0 = (li & 1) * (P / 2);
+                    const T t = st[qq][0];
+                    const T u0 = (T)(j0 - (P / 2 - 1)) - t;
+                    T w = exp(-wa.beta * u0 * u0);
+                    T r = exp(-wa.beta * ((T)2 * u0 + (T)1));
 #pragma unroll
-                    for (int k = 0; k < P; ++k) swx[q0 + lane][k] = wv[k];
+                    for (int l = 0; l < P / 2; ++l) {
+                        swx[qq][j0 + l] = (j0 + l == P - 1 && t == (T)0) ? (T)0 : w;
+                        w *= r;
+                        r *= e2;
+                    }
                 }
                 // y and z weights of the patch's lines, one lane per (particle, axis): line l is at
                 // stencil offset j = l - o and distance u0 + l from the particle, and the Gaussian
@@ -254,7 +262,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_p2g_sweep(const typename RecVie
                 }
             }
             wave_lds_sync();
-#pragma unroll (P <= 12 ? 2 : 1)
+#pragma unroll 2
             for (int q = q0; q < q0 + cnt; ++q) {
                 const T wy = swy[q][ly];
                 const T g0 = wy * swz[q][0][lz], g1 = wy * swz[q][1][lz], g2 = wy * swz[q][2][lz];

@@ -7,17 +7,16 @@
 
 namespace ewald {
 
-constexpr int kMaxP = 16;
 constexpr int kKbDeg = 14;  // degree of the per-offset Kaiser-Bessel weight polynomials
 
 // Per-plan window constants for one precision.  Gaussian: w0(u) = exp(-beta u^2) with u the
-// distance to the particle in grid spacings, and ratio[j] = exp(-beta (2j + 1)).
+// distance to the particle in grid spacings (P2G evaluates it at consecutive points by the
+// recurrence w0(u + 1) = w0(u) exp(-beta (2u + 1)), the fast Gaussian gridding factorisation).
 // Kaiser-Bessel (kb != nullptr): kb[j * (kKbDeg + 1) + k] are the monomial coefficients, in
 // s = 2t - 1, of the weight of stencil offset j as a function of the fraction t in [0, 1).
 template <typename T>
 struct WinArgs {
     T beta;
-    T ratio[kMaxP];
     const T* kb;
 };
 
@@ -30,30 +29,10 @@ __device__ inline T kb_weight(const T* __restrict__ c, T s)
     return q;
 }
 
-// The P weights of the stencil of a particle with fraction t = y/h - floor(y/h):
-// w[j] = w0(j - (P/2 - 1) - t), j = 0..P-1 (grid points floor(y/h) - P/2 + 1 + j).
-// Uses the recurrence w[j+1] = w[j] * exp(-beta (2j+1)) * exp(2 beta m0), m0 = P/2 - 1 + t
-// (two exponentials per particle and axis instead of P; the fast Gaussian gridding
-// factorisation).  The window's support is open: the point at distance exactly P h/2
-// (t == 0, j = P-1) gets weight 0.
-template <typename T, int P>
-__device__ inline void window_weights(T t, const WinArgs<T>& wa, T* w)
-{
-    if (wa.kb) {
-        const T s = (T)2 * t - (T)1;
-#pragma unroll
-        for (int j = 0; j < P; ++j) w[j] = kb_weight<T>(wa.kb + j * (kKbDeg + 1), s);
-    } else {
-        const T m0 = (T)(P / 2 - 1) + t;
-        const T E = exp((T)2 * wa.beta * m0);
-        w[0] = exp(-wa.beta * m0 * m0);
-#pragma unroll
-        for (int j = 0; j + 1 < P; ++j) w[j + 1] = w[j] * (wa.ratio[j] * E);
-    }
-    if (t == (T)0) w[P - 1] = (T)0;
-}
-
-// The weight of one stencil offset j (0 <= j < P).
+// The stencil of a particle with fraction t = y/h - floor(y/h) has the P grid points
+// floor(y/h) - P/2 + 1 + j, j = 0..P-1, with weights w0(j - (P/2 - 1) - t).  The window's
+// support is open: the point at distance exactly P h/2 (t == 0, j = P-1) gets weight 0.
+// window_weight_one is the weight of one stencil offset j (0 <= j < P).
 template <typename T, int P>
 __device__ inline T window_weight_one(int j, T t, const WinArgs<T>& wa)
 {
@@ -74,7 +53,6 @@ inline WinArgs<T> make_win_args(const Plan& pl)
 {
     WinArgs<T> wa;
     wa.beta = (T)pl.beta;
-    for (int j = 0; j < kMaxP; ++j) wa.ratio[j] = (T)exp(-pl.beta * (2.0 * j + 1.0));
     wa.kb = nullptr;
     if (pl.window_kb) wa.kb = (const T*)(sizeof(T) == 8 ? (const void*)pl.d_kb64 : (const void*)pl.d_kb32);
     return wa;
