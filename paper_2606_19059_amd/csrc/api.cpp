@@ -188,7 +188,7 @@ constexpr double kFourierFp32MinTol = 1e-6;
 // ---- plan cost model (MI355X) ----
 // Device time of one evaluation, per stage, fitted to stage timings measured on one
 // MI355X (uniform particles in the unit cube, N = 3e3..3e6, grids 16^3..256^3, both
-// modes; median error 3-14% per stage).  Used to choose the grid when nothing but the
+// modes; median error 4-17% per stage).  Used to choose the grid when nothing but the
 // tolerance is given: every power-of-two grid is resolved by the error split and the
 // cheapest one is taken.
 struct CostModel {
@@ -198,10 +198,10 @@ struct CostModel {
     double fft_cell, fft0;
     double sort, sort_cell, sort0;
 };
-constexpr CostModel kCost64 = {6.766, 0.222, 0.272, 0.152, 0.093, 0.984, 0.052, 0.110, 0.062, 0.086, 0.028,
-                               0.202, 0.009, 0.045};
-constexpr CostModel kCost32 = {5.709, 0.237, 0.315, 0.136, 0.146, 0.566, 0.059, 0.062, 0.053, 0.055, 0.037,
-                               0.232, 0.005, 0.045};
+constexpr CostModel kCost64 = {6.437, 0.199, 0.108, 0.169, 0.072, 0.964, 0.053, 0.117, 0.062, 0.086, 0.028,
+                               0.216, 0.008, 0.044};
+constexpr CostModel kCost32 = {5.462, 0.245, 0.146, 0.171, 0.059, 0.561, 0.068, 0.061, 0.051, 0.055, 0.037,
+                               0.223, 0.006, 0.044};
 constexpr double kWaveSlots = 2048.0;  // concurrent P2P waves at which the chip is full
 
 int p2g_blocks(const int M[3], int P)
