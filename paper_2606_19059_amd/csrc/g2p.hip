@@ -82,18 +82,44 @@ __global__ __launch_bounds__(64) void k_g2p(int n, const typename RecView<T>::Re
     const TG* __restrict__ g1 = grid + nc;
     const TG* __restrict__ g2 = grid + 2 * nc;
     const int64_t nn = n;
+    const T e2 = exp((T)-2 * wa.beta);  // ratio of consecutive Gaussian recurrence factors
     const int s0 = xcd_remap((int)blockIdx.x, (int)gridDim.x) * kG2PGroup;
     const int s1 = min(s0 + kG2PGroup, n);
     for (int sg = s0; sg < s1; sg += kG2PGroup) {
         // weights and stencil anchors of the group's targets (missing targets repeat the last)
-        for (int k = lane; k < kG2PGroup * 3 * P; k += kWave) {
-            const int qq = k / (3 * P), d = (k / P) % 3, jj = k % P;
-            int c[3];
-            T t[3], f[3];
-            RecView<T>::load(rec[min(sg + qq, s1 - 1)], g, c, t, f);
-            const T td = (d == 0) ? t[0] : (d == 1 ? t[1] : t[2]);
-            sw[qq][d][jj] = window_weight_one<T, P>(jj, td, wa);
-            if (jj == 0) anc[qq][d] = c[d] - P / 2 + 1;
+        if (sizeof(T) == 8 && !wa.kb) {
+            // FP64 Gaussian: two lanes per (target, axis), each walking P/2 weights away from
+            // the peak by the recurrence w(u + s) = w(u) exp(-beta (2 s u + 1)), s = -1 for
+            // offsets P/2-1 down to 0 and s = +1 for P/2 up to P-1 (two exponentials per lane)
+            for (int k = lane; k < kG2PGroup * 6; k += kWave) {
+                const int qq = k / 6, d = (k >> 1) % 3, up = k & 1;
+                int c[3];
+                T t[3], f[3];
+                RecView<T>::load(rec[min(sg + qq, s1 - 1)], g, c, t, f);
+                const T td = (d == 0) ? t[0] : (d == 1 ? t[1] : t[2]);
+                const T sgn = up ? (T)1 : (T)-1;
+                const T u0 = (T)up - td;  // distance of offset P/2 - 1 + up
+                T w = exp(-wa.beta * u0 * u0);
+                T r = exp(-wa.beta * ((T)2 * sgn * u0 + (T)1));
+#pragma unroll
+                for (int l = 0; l < P / 2; ++l) {
+                    const int jj = up ? P / 2 + l : P / 2 - 1 - l;
+                    sw[qq][d][jj] = (jj == P - 1 && td == (T)0) ? (T)0 : w;
+                    w *= r;
+                    r *= e2;
+                }
+                if (!up) anc[qq][d] = (d == 0 ? c[0] : (d == 1 ? c[1] : c[2])) - P / 2 + 1;
+            }
+        } else {
+            for (int k = lane; k < kG2PGroup * 3 * P; k += kWave) {
+                const int qq = k / (3 * P), d = (k / P) % 3, jj = k % P;
+                int c[3];
+                T t[3], f[3];
+                RecView<T>::load(rec[min(sg + qq, s1 - 1)], g, c, t, f);
+                const T td = (d == 0) ? t[0] : (d == 1 ? t[1] : t[2]);
+                sw[qq][d][jj] = window_weight_one<T, P>(jj, td, wa);
+                if (jj == 0) anc[qq][d] = c[d] - P / 2 + 1;
+            }
         }
         __syncthreads();
         const int ax = anc[q][0], ay = anc[q][1], az = anc[q][2];
