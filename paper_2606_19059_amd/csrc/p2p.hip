@@ -142,15 +142,14 @@ __device__ inline void coef64(double r2, const PairArgs& a, double& a1, double& 
     b = Cr * (rinv * rinv);
 }
 
-// FP32 versions (FP32 bulk mode): hardware reciprocal, rsqrt (+ one Newton step) and exp2,
-// degree-11 polynomial.  The exponent -xi^2 r^2 log2(e) reaches ~40, where one FP32 ulp is
+// FP32 versions (FP32 bulk mode): hardware reciprocal, rsqrt and exp2 (1 ulp each, used
+// as they come: a refinement step would only chase FP32's own rounding), degree-11 polynomial.  The exponent -xi^2 r^2 log2(e) reaches ~40, where one FP32 ulp is
 // ~4e-6, so it is formed and split into integer and fraction in FP64 (same VALU rate) and
 // only 2^fraction is taken in FP32.
 __device__ inline float screen_q32(float x, const PairArgs& a)
 {
     const float d = x + (float)kScreenK;
-    float r = __builtin_amdgcn_rcpf(d);
-    r = fmaf(fmaf(-d, r, 1.0f), r, r);
+    const float r = __builtin_amdgcn_rcpf(d);  // 1 ulp: no refinement needed in FP32
     const float u = fmaf((x - (float)kScreenK) * r, (float)kScreenA, (float)kScreenB);
     float q = a.c32[kScreenDeg32];
 #pragma unroll
@@ -161,15 +160,14 @@ __device__ inline float screen_q32(float x, const PairArgs& a)
 __device__ inline void coef32(double r2d, const PairArgs& a, float& a1, float& b)
 {
     const float r2 = (float)r2d;
-    const float y = __builtin_amdgcn_rsqf(r2);
-    const float rinv = y * fmaf(-0.5f * r2 * y, y, 1.5f);
+    const float rinv = __builtin_amdgcn_rsqf(r2);  // 1 ulp: no refinement needed in FP32
     const float x = (float)a.xi * r2 * rinv;
     const double ea = -a.xi2_log2e * r2d;
     const double en = rint(ea);
     const float e = ldexpf(__builtin_amdgcn_exp2f((float)(ea - en)), (int)en);
-    const float C = e * screen_q32(x, a);
-    a1 = fmaf(C, rinv, -(float)a.four_xi_over_sqrtpi * e);
-    b = C * rinv * (rinv * rinv);
+    const float Cr = e * screen_q32(x, a) * rinv;
+    a1 = fmaf(-(float)a.four_xi_over_sqrtpi, e, Cr);
+    b = Cr * (rinv * rinv);
 }
 
 // Pair coefficients in the formula precision TF (double: FP64 path, Fast for tol >= 1e-10;
@@ -214,8 +212,7 @@ __device__ inline void coef64_st(double r2, const PairArgs& a, double& a1, doubl
 __device__ inline void coef32_st(double r2d, const PairArgs& a, float& a1, float& b, float& al, float& be)
 {
     const float r2 = (float)r2d;
-    const float y = __builtin_amdgcn_rsqf(r2);
-    const float rinv = y * fmaf(-0.5f * r2 * y, y, 1.5f);
+    const float rinv = __builtin_amdgcn_rsqf(r2);
     const float r = r2 * rinv;
     const float x = (float)a.xi * r;
     const double ea = -a.xi2_log2e * r2d;
