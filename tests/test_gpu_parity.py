@@ -54,6 +54,8 @@ CASES = {
     # points next to the segment boundaries are summed from two segments' halo planes
     "cube64_P8": ((1.0, 1.0, 1.0), (64, 64, 64), 20.0, 0.2, 8, 4.8),
     "xlong_P4": ((4.0, 0.5, 0.5), (128, 16, 16), 12.0, 0.2, 4, 3.0),
+    # a box 64 times longer in z than across: one tile (8^3 cells) in x and y, 64 along z
+    "zlong_P8": ((0.25, 0.25, 16.0), (8, 8, 512), 30.0, 0.1, 8, 4.8),
 }
 
 
@@ -73,7 +75,7 @@ def test_tiny_eval_runs():
 
 @pytest.mark.parametrize("name,n", [("cube32_P8", 2000), ("aniso_P12", 1531), ("grid8_P8", 300),
                                     ("long_P6", 2049), ("cube16_P16", 700), ("cube64_P8", 3000),
-                                    ("xlong_P4", 2500)])
+                                    ("xlong_P4", 2500), ("zlong_P8", 3000)])
 def test_p2g_grid_matches_oracle(name, n):
     E = _E()
     box, grid, xi, rc, P, m = CASES[name]
@@ -97,7 +99,7 @@ def test_far_grid_matches_oracle(name, n):
 
 
 @pytest.mark.parametrize("name,n", [("cube32_P8", 2000), ("aniso_P12", 1531), ("grid8_P8", 333),
-                                    ("long_P6", 1200), ("cube16_P16", 501)])
+                                    ("long_P6", 1200), ("cube16_P16", 501), ("zlong_P8", 3000)])
 def test_near_and_far_fields_match_oracle(name, n):
     E = _E()
     box, grid, xi, rc, P, m = CASES[name]
