@@ -117,6 +117,68 @@ def timed_evals(plan, x, f, steps, warmup):
     return float(np.median(tot)), u
 
 
+def config_leg(E, name, steps, warmup, n_targets, dev):
+    """One benchmark configuration, timed as the main workload: median device ms of `steps`
+    evaluations, per-stage times and rooflines (P2P priced on the exact pair count), the
+    sampled error against the classical oracle, and for FP32 bulk the whole-N error against
+    the FP64 GPU path at a tighter tolerance on the same grid."""
+    import torch
+
+    import oracle
+    from paper_2606_19059_amd import workloads as W
+
+    wl = W.WORKLOADS[name]
+    x_np, f_np = wl.make()
+    x = torch.from_numpy(x_np).to(dev)
+    f = torch.from_numpy(f_np).to(dev)
+    plan = E.Plan(wl.box, wl.tol, grid=wl.grid, precision=wl.precision, n_max=wl.n, timers=True)
+    info = plan.info
+    ws = plan.workspace(wl.n, dev)
+    u = torch.empty_like(x)
+    for _ in range(warmup):
+        plan.eval(x, f, out=u, workspace=ws)
+    torch.cuda.synchronize()
+    acc = {k: 0.0 for k in E.STAGES}
+    tot = []
+    for _ in range(steps):
+        plan.eval(x, f, out=u, workspace=ws)
+        torch.cuda.synchronize()
+        st = plan.stage_ms()
+        tot.append(st["total"])
+        for k in st:
+            acc[k] += st[k] / steps
+    ms = float(np.median(tot))
+    pairs = plan.count_pairs(x, f, workspace=ws)
+    real = 8 if wl.precision == "fp64" else 4
+    ncell = info["grid"][0] * info["grid"][1] * info["grid"][2]
+    peak = FP64_VECTOR_TFLOPS if wl.precision == "fp64" else FP32_VECTOR_TFLOPS
+    out = {
+        "workload": "%s: N=%d %s in box %s, tol %g, grid %s, P=%d (Gaussian, derived from tol), %s"
+                    % (wl.name, wl.n, wl.dist, "x".join("%g" % b for b in wl.box), wl.tol,
+                       "x".join(str(m) for m in info["grid"]), info["P"], wl.precision),
+        "ms_median": ms, "particles_per_s": wl.n / (ms * 1e-3), "stage_ms": acc,
+        "ordered_pairs_in_rc": pairs, "xi": info["xi"], "r_c": info["r_c"], "P": info["P"],
+        "stage_roofline": stage_roofline(acc, wl.n, ncell, info["P"], real, pairs, peak),
+    }
+    u_np = u.cpu().numpy()
+    if n_targets >= wl.n:
+        ref = oracle.ewald_sum(x_np, f_np, wl.box)
+        out["rel_err_oracle"] = oracle.rel_err(u_np, ref)
+        out["oracle_targets"] = "all %d" % wl.n
+    else:
+        tgt = W.sample_targets(wl.n, n_targets, seed=100 + int(name[1:]))
+        out["rel_err_oracle"] = oracle.rel_err(u_np[:, tgt], oracle.ewald_sum(x_np, f_np, wl.box, targets=tgt))
+        out["oracle_targets"] = "%d seeded" % n_targets
+    if wl.precision == "fp32":
+        p64 = E.Plan(wl.box, min(wl.tol, 1e-8), grid=wl.grid, precision="fp64", n_max=wl.n)
+        u64 = p64.eval(x, f)
+        out["rel_err_vs_fp64_path_all_n"] = float((torch.linalg.norm(u - u64) / torch.linalg.norm(u64)).item())
+        del p64, u64
+    del plan, ws, u, x, f
+    torch.cuda.empty_cache()
+    return out
+
+
 def serving_leg(n_requests):
     """Stream of independent suspensions (N log-uniform in [1e3, 1e6], cubic or 1x1x2 box,
     uniform or blobs, tol in {1e-4, 1e-6, 1e-8}): saturated throughput with every request
@@ -185,6 +247,8 @@ def main():
                     help="skip the cost-model plan and Kaiser-Bessel legs")
     ap.add_argument("--serve-requests", type=int, default=200,
                     help="requests in the serving leg (Poisson stream of independent suspensions; 0: skip)")
+    ap.add_argument("--configs", default="c1,c3,c4",
+                    help="other benchmark configurations timed beside the main one (comma list; '' for none)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -273,9 +337,24 @@ def main():
                       "structure factor included), %.1f s" % (len(tgt), wl.n, cpu_s),
         }
         log("sampled rel err vs oracle: %.3e (tol %g); oracle %.2f s" % (rel_err, wl.tol, cpu_s))
+        # the same oracle on one host core, on a smaller sample of the same targets
+        threads = oracle.num_threads()
+        n1 = int(max(8, min(len(tgt), len(tgt) * 0.4 / max(threads, 1))))
+        oracle.set_num_threads(1)
+        try:
+            tc = time.perf_counter()
+            oracle.ewald_sum(x_np, f_np, wl.box, targets=tgt[:n1])
+            one_s = time.perf_counter() - tc
+        finally:
+            oracle.set_num_threads(threads)
+        cpu["value_1core"] = n1 / one_s
+        cpu["sample_1core"] = "%d of the same targets on 1 thread, %.1f s" % (n1, one_s)
+        log("oracle on 1 core: %.2f particles/s" % cpu["value_1core"])
 
-    # roofline of the dominant kernel (P2P): algorithmic flops per launch / its mean time
-    pairs = p2p_pairs_uniform(wl.n, wl.box, info["r_c"]) if wl.dist == "uniform" else None
+    # roofline of the dominant kernel (P2P): algorithmic flops per launch / its mean time,
+    # on the exact number of ordered pairs inside r_c (the library's count-only pass)
+    pairs = plan.count_pairs(x, f, workspace=ws)
+    log("ordered pairs in r_c: %d (uniform expectation %.4g)" % (pairs, p2p_pairs_uniform(wl.n, wl.box, info["r_c"])))
     p2p_s = stages["p2p"] * 1e-3
     peak = FP64_VECTOR_TFLOPS if precision == "fp64" else FP32_VECTOR_TFLOPS
     achieved = (pairs * P2P_FLOPS_PER_PAIR / p2p_s / 1e12) if pairs else None
@@ -353,6 +432,12 @@ def main():
     p2g_bytes = wl.n * 6 * real + 3 * ncell * real
     p2g_gbs = p2g_bytes / (stages["p2g"] * 1e-3) / 1e9 if stages["p2g"] > 0 else None
     per_stage = stage_roofline(stages, wl.n, ncell, info["P"], real, pairs, peak)
+    configs = {}
+    for name in [c for c in args.configs.split(",") if c and c != wl.name]:
+        cw = W.WORKLOADS[name]
+        n_t = cw.n if cw.n <= 1000 else (64 if cw.n <= 4_000_000 else 48)
+        configs[name] = config_leg(E, name, 20 if cw.n <= 1000 else 10, 3 if cw.n <= 1000 else 2, n_t, dev)
+        log("config %s:" % name, json.dumps(configs[name]))
     serving = None
     if args.serve_requests > 0:
         serving = serving_leg(args.serve_requests)
@@ -383,6 +468,7 @@ def main():
             "p2g_GBs": p2g_gbs, "p50_ms": p50, "p99_ms": p99, "stage_roofline": per_stage,
         },
         "serving": serving,
+        "configs": configs,
         "other_plans": legs,
         "roofline": roofline,
         "cpu_baseline": cpu,

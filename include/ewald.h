@@ -54,26 +54,31 @@ typedef enum {
 /* Precision modes (low byte of ewald_params.precision) and flags (OR'd in). */
 enum {
     EWALD_FP64 = 0,      /* every step in FP64 */
-    EWALD_FP32_BULK = 1, /* P2P, P2G, FFT, G2P in FP32; Fourier-space scaling, k = 0 and
-                            self terms, final sum in FP64.  Below tol 1e-6 the grid and its
-                            transforms are kept in FP64 (the FP32 round trip through the
-                            3D FFT alone leaves ~2e-7 relative error); P2P and the window
-                            weights of G2P stay FP32.  All sums over pairs and stencils
-                            accumulate in FP64 */
-    EWALD_FLAG_P2P_FP64_ACC = 1 << 8, /* accepted for compatibility: the near-field sums are
-                                         always accumulated in FP64 (in FP32 bulk too: FP64
-                                         LDS atomics are fast on gfx950, FP32 ones are not) */
+    EWALD_FP32_BULK = 1, /* the pair formula of P2P, the window weights of P2G and G2P and (for
+                            tol >= 1e-6) the grid, FFT, CNV input/output and IFFT in FP32.  P2G
+                            computes its sums in FP64 and stores them to the FP32 grid; below
+                            tol 1e-6 the grid and its transforms stay FP64 (the FP32 round trip
+                            through the 3D FFT alone leaves ~2e-7 relative error).  Positions,
+                            the cutoff test, the Fourier-space scaling, the k = 0 and self
+                            terms and the final sum are FP64, and every sum over pairs or
+                            stencil points accumulates in FP64 */
+    EWALD_FLAG_P2P_FP64_ACC = 1 << 8, /* deprecated, no effect: the near-field sums are always
+                                         accumulated in FP64 (in FP32 bulk too: FP64 LDS
+                                         atomics are fast on gfx950, FP32 ones are not) */
     EWALD_FLAG_STAGE_TIMERS = 1 << 9, /* record per-stage HIP events (see ewald_stage_ms); the
                                          events belong to the plan, so overlapping evaluations
                                          of one timed plan on several streams time nothing
                                          meaningful: time one evaluation at a time */
     EWALD_FLAG_WINDOW_KB = 1 << 10,   /* truncated Kaiser-Bessel window (Sec. 2.2) instead of the
                                          Gaussian: w0(d) = I0(beta sqrt(1 - (2d/(P h))^2)) / I0(beta) */
-    EWALD_FLAG_DETERMINISTIC = 1 << 11, /* bitwise reproducible results: P2P evaluates every pair
-                                          from both sides (about twice the pair work).  Without it
-                                          each pair is evaluated once and its two contributions
-                                          are added with atomics, so repeated evaluations agree to
-                                          rounding (~1e-16 relative), not bitwise */
+    EWALD_FLAG_DETERMINISTIC = 1 << 11, /* bitwise reproducible results for the same inputs on the
+                                          same device: P2P evaluates every pair from both sides
+                                          (about 1.5x the P2P time) and sums in a fixed order; the
+                                          particles of every grid cell are ordered by input index
+                                          whatever the cell's size.  Without it each pair is
+                                          evaluated once and its two contributions are added with
+                                          atomics, so repeated evaluations agree to rounding
+                                          (~1e-16 relative), not bitwise */
     EWALD_FLAG_STRESSLET = 1 << 12     /* the plan also evaluates stresslet (double-layer) sources
                                           with ewald_eval_combined: its workspace holds the sorted
                                           source tensors and a 9-component grid.  Not combinable
@@ -82,12 +87,12 @@ enum {
 
 /*
  * Plan parameters.  Any parameter given as <= 0 is derived from `tol`
- * following the error split of Sec. 2.3 (eq. (ese), each error term held to
+ * following the error split of Sec. 2.4 (eq. (ese), each error term held to
  * tol/3): xi from the grid spacing (E^F), r_c from xi (E^N), the window
  * support P and shape from the window's error model.  When grid, xi and r_c
  * are all left to derive, every power-of-two grid is resolved this way and the
  * one with the smallest predicted device time for n_max particles is taken
- * (the plan cost model, Sec. 2.3's parameter choice made by measured cost);
+ * (the plan cost model, Sec. 2.4's parameter choice made by measured cost);
  * when xi or r_c is given, the grid is the coarsest that resolves xi.
  */
 typedef struct {
@@ -118,6 +123,10 @@ typedef struct {
     int64_t workspace_bytes;  /* ewald_workspace_bytes(plan, n_max) */
     double predicted_ms;      /* device time of one evaluation of n_max particles predicted by
                                  the plan cost model (uniform particles; MI355X-calibrated) */
+    double self_coef;         /* c of the self term -c f_i: c = 4 xi / sqrt(pi), the limit of
+                                 G - G^N at r = 0 (so u = u_near + u_far - c f) */
+    int64_t grid_bytes;       /* bytes of the grid ewald_spread and ewald_far_grid write:
+                                 3 M1 M2 M3 elements of 8 bytes when fourier_fp64, else 4 */
 } ewald_plan_info;
 
 /* Create a plan (host call; allocates the plan's small device tables on the
@@ -152,7 +161,7 @@ int ewald_eval(ewald_plan_t plan, int64_t n, const double* x, const double* f, d
                void* workspace, int64_t workspace_bytes, void* stream);
 
 /*
- * Combined single and double layer sources (Sec. 2.2, "Combined single and double
+ * Combined single and double layer sources (Sec. 2.3, "Combined single and double
  * layers"): every particle j carries a force f_j and two vectors q_j, n_j, and
  *   u(x_i) = sum_j sum_p' [ G(x_i - x_j + p) f_j + T(x_i - x_j + p) (q_j n_j^T) ]
  * with the stresslet T_abc(r) = -6 r_a r_b r_c / |r|^5 (component a of T (q n^T) is
@@ -185,21 +194,34 @@ int ewald_eval_parts(ewald_plan_t plan, int64_t n, const double* x, const double
 
 /*
  * Diagnostic: the P2G grid phi (eq. (p2g), no h^3 factor) as (3, M1, M2, M3)
- * row-major (M3 fastest), in the plan's grid precision (double for
- * EWALD_FP64, float for EWALD_FP32_BULK).  `grid` is device memory of
- * 3*M1*M2*M3 elements.
+ * row-major (M3 fastest).  Element type: double when ewald_plan_info.fourier_fp64
+ * is 1 (every FP64 plan, and FP32-bulk plans below tol 1e-6), else float.  `grid`
+ * is caller-owned device memory of grid_bytes bytes; EWALD_ENOMEM (nothing
+ * enqueued) when grid_bytes is below ewald_plan_info.grid_bytes.  Other errors as
+ * ewald_eval.
  */
 int ewald_spread(ewald_plan_t plan, int64_t n, const double* x, const double* f, void* grid,
-                 void* workspace, int64_t workspace_bytes, void* stream);
+                 int64_t grid_bytes, void* workspace, int64_t workspace_bytes, void* stream);
 
 /*
  * Diagnostic: the real grid that G2P interpolates, after P2G, FFT, CNV
  * (eq. (sca)) and IFFT, stored as h1 h2 h3 * v(g_l) of eq. (g2p) (the h^3
- * factor and the inverse-DFT normalisation are folded into CNV), layout and
- * precision as for ewald_spread.
+ * factor and the inverse-DFT normalisation are folded into CNV); layout, element
+ * type, size check and errors as for ewald_spread.
  */
 int ewald_far_grid(ewald_plan_t plan, int64_t n, const double* x, const double* f, void* grid,
-                   void* workspace, int64_t workspace_bytes, void* stream);
+                   int64_t grid_bytes, void* workspace, int64_t workspace_bytes, void* stream);
+
+/*
+ * Diagnostic for measurement: the exact number of ordered pairs (i, j), i != j, over all
+ * periodic images p with 0 < |x_i - x_j + p| < r_c -- the pairs the near-field sum of
+ * Sec. 2.1 (eq. (potentials-near)) runs over -- written to `count`, one uint64_t in
+ * device memory (overwritten; n = 0 writes 0).  Runs the sort and a count-only pass of the
+ * one-sided P2P over the same cell walk; computes no pair formula.  Arguments and errors
+ * otherwise as ewald_eval (f is read by the sort).
+ */
+int ewald_count_pairs(ewald_plan_t plan, int64_t n, const double* x, const double* f, uint64_t* count,
+                      void* workspace, int64_t workspace_bytes, void* stream);
 
 /*
  * Per-stage device times (ms) of the last evaluation made with this plan when

@@ -56,12 +56,18 @@ def _load():
         lib.ewo_real_space_st.argtypes = [i64, dp, dp, i64, ip, dp, ctypes.c_double, ctypes.c_double, dp]
         lib.ewo_recip_st.argtypes = [i64, dp, dp, i64, ip, dp, ctypes.c_double, ctypes.c_double, dp]
         lib.ewo_num_threads.restype = ctypes.c_int
+        lib.ewo_set_num_threads.argtypes = [ctypes.c_int]
         _lib = lib
     return _lib
 
 
 def num_threads() -> int:
     return int(_load().ewo_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the following oracle calls (for timing on fewer cores)."""
+    _load().ewo_set_num_threads(int(n))
 
 
 def _dptr(a: np.ndarray):
@@ -200,7 +206,7 @@ def ewald_sum(x, f, L, targets=None, xi=None, parts=False, q=None, nrm=None):
     xi_o is the oracle's own split parameter (the result does not depend on it);
     r_cut = 6/xi_o and k_max = 12 xi_o put both truncations below 1e-15.  With ``q`` and
     ``nrm`` (3, n) the stresslet sources q n^T of the combined single and double layer sum
-    (Sec. 2.2) are added.  Returns (3, n_targets), or (total, real, recip, self) when ``parts``.
+    (Sec. 2.3) are added.  Returns (3, n_targets), or (total, real, recip, self) when ``parts``.
     """
     x, f, L = _prep(x, f, L)
     n = x.shape[1]

@@ -63,6 +63,16 @@ int ewo_num_threads(void)
 #endif
 }
 
+/* Threads of the following calls (timing the oracle on fewer cores; arithmetic unchanged). */
+void ewo_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /*
  * Real-space (near-field) sum at split parameter xi and cutoff r_cut.
  * Every image p in Z^3 L with 0 < |x_i - x_j + p| < r_cut contributes

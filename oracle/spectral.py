@@ -142,7 +142,7 @@ def cnv(phihat, L, M, xi, P, m, window="gaussian"):
 
 
 def cnv_stresslet(shat, L, M, xi, P, m, window="gaussian"):
-    """The stresslet part of the combined CNV (Sec. 2.2, combined layers): 9 grid components in,
+    """The stresslet part of the combined CNV (Sec. 2.3, combined layers): 9 grid components in,
     3 out, vhat_a(k) = i A(k) / what(k)^2 P_abc(k) Shat_bc(k) with A = 8 pi / k^4 (1 + k^2/4 xi^2)
     e^{-k^2/4 xi^2} and P_abc = k^2 (delta_bc k_a + delta_ab k_c + delta_ac k_b) - 2 k_a k_b k_c.
     ``shat``: (9, M1, M2, M3) complex, row 3 b + c.  Zeroes k = 0 and the Nyquist planes."""

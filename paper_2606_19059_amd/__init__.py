@@ -9,7 +9,6 @@ fallback.
 from __future__ import annotations
 
 import ctypes
-import math
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -43,6 +42,7 @@ EXPORTS = (
     "ewald_eval_combined_parts",
     "ewald_spread",
     "ewald_far_grid",
+    "ewald_count_pairs",
     "ewald_stage_ms",
     "ewald_last_error",
     "ewald_version",
@@ -83,6 +83,8 @@ class PlanInfo(ctypes.Structure):
         ("fourier_fp64", ctypes.c_int32),
         ("workspace_bytes", ctypes.c_int64),
         ("predicted_ms", ctypes.c_double),
+        ("self_coef", ctypes.c_double),
+        ("grid_bytes", ctypes.c_int64),
     ]
 
 
@@ -114,7 +116,8 @@ def load(path: str | None = None):
         getattr(lib, name).argtypes = [vp, i64, vp, vp, vp, vp, vp] + (
             [vp] if name == "ewald_eval_combined_parts" else []) + [vp, i64, vp]
     for name in ("ewald_spread", "ewald_far_grid"):
-        getattr(lib, name).argtypes = [vp, i64, vp, vp, vp, vp, i64, vp]
+        getattr(lib, name).argtypes = [vp, i64, vp, vp, vp, i64, vp, i64, vp]
+    lib.ewald_count_pairs.argtypes = [vp, i64, vp, vp, vp, vp, i64, vp]
     lib.ewald_stage_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32]
     lib.ewald_last_error.restype = ctypes.c_char_p
     lib.ewald_version.restype = ctypes.c_char_p
@@ -187,6 +190,8 @@ def _info_dict(info, precision):
         "stencil": tuple(info.stencil), "workspace_bytes": info.workspace_bytes,
         "fourier_fp64": bool(info.fourier_fp64),
         "predicted_ms": info.predicted_ms,
+        "self_coef": info.self_coef,
+        "grid_bytes": info.grid_bytes,
         "window": "kb" if q.precision & EWALD_FLAG_WINDOW_KB else "gaussian",
         "deterministic": bool(q.precision & EWALD_FLAG_DETERMINISTIC),
         "stresslet": bool(q.precision & EWALD_FLAG_STRESSLET),
@@ -205,7 +210,7 @@ class Plan:
     """A resolved spectral Ewald plan (parameters, tables) for one box and tolerance.
 
     ``precision``: "fp64" or "fp32" (FP32 bulk).  Parameters left as None are derived
-    from ``tol`` (Sec. 2.3).  Owns a cached workspace for ``eval`` calls that do not
+    from ``tol`` (Sec. 2.4).  Owns a cached workspace for ``eval`` calls that do not
     pass their own.
     """
 
@@ -239,7 +244,8 @@ class Plan:
 
     @property
     def self_coef(self):
-        return 4.0 * self.info["xi"] / math.sqrt(math.pi)
+        """c of the self term -c f (the library's value, ewald_plan_info.self_coef)."""
+        return self.info["self_coef"]
 
     def workspace_bytes(self, n):
         return _check(load().ewald_workspace_bytes(self._h, int(n)))
@@ -314,7 +320,8 @@ class Plan:
         dt = torch.float64 if self.info["fourier_fp64"] else torch.float32
         g = torch.empty((3, M[0], M[1], M[2]), dtype=dt, device=x.device)
         wp, wb = self._ws_args(n, workspace, x.device)
-        _check(fn(self._h, n, _ptr(x), _ptr(f), _ptr(g), wp, wb, _stream_handle(stream)))
+        _check(fn(self._h, n, _ptr(x), _ptr(f), _ptr(g), ctypes.c_int64(g.numel() * g.element_size()), wp, wb,
+                  _stream_handle(stream)))
         return g
 
     def spread(self, x, f, workspace=None, stream=None):
@@ -324,6 +331,19 @@ class Plan:
     def far_grid(self, x, f, workspace=None, stream=None):
         """h1 h2 h3 * v(g_l): the grid G2P interpolates (after FFT, CNV, IFFT)."""
         return self._grid_call(load().ewald_far_grid, x, f, workspace, stream)
+
+    def count_pairs(self, x, f, workspace=None, stream=None):
+        """Exact number of ordered pairs within r_c (all images, i != j): the near-field sum's
+        pairs.  Synchronises the stream to read the device counter."""
+        import torch
+
+        n = _check_particles(x, f)
+        c = torch.zeros(1, dtype=torch.int64, device=x.device)
+        wp, wb = self._ws_args(n, workspace, x.device)
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(load().ewald_count_pairs(self._h, n, _ptr(x), _ptr(f), _ptr(c), wp, wb, _stream_handle(s)))
+        s.synchronize()
+        return int(c.item())
 
     def stage_ms(self):
         """Per-stage device ms of the last evaluation (plan created with timers=True)."""

@@ -56,7 +56,7 @@ int next_pow2(double v)
     return p;
 }
 
-// ---- error estimates, Sec. 2.3 eq. (ese) (unit box, unit force norm) ----
+// ---- error estimates, Sec. 2.4 eq. (ese) (unit box, unit force norm) ----
 
 double err_near(double xi, double rc)
 {
@@ -302,6 +302,7 @@ int64_t layout_work(const Plan& pl, int64_t n, char* base, Work* w)
     o->start = (int*)take(4 * ((int64_t)g.ncells + 1));
     o->chunk_off = (int*)take(4 * ((int64_t)g.ntiles + 1));
     o->part = (int*)take(4 * (int64_t)scan_part_elems(std::max(g.ncells, g.ntiles)));
+    o->cell_lists = (int*)take(4 * cell_list_elems(nn));
     o->rec = (void*)take((int64_t)recsz * nn);
     o->u_near = (double*)take(8 * 3 * nn);
     o->srec = pl.stresslet ? (double*)take(8 * 6 * nn) : nullptr;
@@ -465,8 +466,10 @@ int validate_and_resolve(const ewald_params* in, Plan* pl)
         info.h[d] = g.h[d];
         info.n_tiles[d] = g.NT[d];
         info.stencil[d] = g.S[d];
-    info.fourier_fp64 = pl->grid64 ? 1 : 0;
     }
+    info.fourier_fp64 = pl->grid64 ? 1 : 0;
+    info.self_coef = 4.0 * p.xi / std::sqrt(M_PI);
+    info.grid_bytes = (int64_t)3 * g.ncells * (pl->grid64 ? 8 : 4);
     info.err_near = err_near(p.xi, p.r_c);
     info.err_far = err_far(p.xi, h);
     info.err_window = kb ? err_window_kb(p.P, h, p.xi) : err_window(p.P, p.window_shape, h, p.xi);
@@ -556,7 +559,6 @@ int build_tables(Plan* pl)
     for (int a = 0; a < 4; ++a) {
         pl->tw_off[a] = (int)(tw64.size() / 2);
         for (int j = 0; j < tl[a]; ++j) {
-            // angle reduced to the first octant by symmetry for accuracy
             const double ang = -2.0 * M_PI * (double)j / tl[a];
             const double c = std::cos(ang), s = std::sin(ang);
             tw64.push_back(c);
@@ -606,12 +608,19 @@ int check_eval_args(ewald_plan_t plan, int64_t n, const void* x, const void* f, 
     return EWALD_OK;
 }
 
-enum class Out { Full, Parts, Spread, FarGrid };
+enum class Out { Full, Parts, Spread, FarGrid, CountPairs };
 
 int run(ewald_plan_t plan, int64_t n64, const double* x, const double* f, void* o1, void* o2, void* ws,
-        int64_t wsb, void* stream, Out what, bool st = false, const double* q = nullptr, const double* nrm = nullptr)
+        int64_t wsb, void* stream, Out what, bool st = false, const double* q = nullptr, const double* nrm = nullptr,
+        int64_t out_bytes = 0)
 {
     Work w;
+    if ((what == Out::Spread || what == Out::FarGrid) && plan) {
+        const int64_t need = reinterpret_cast<const Plan*>(plan)->info.grid_bytes;
+        if (n64 > 0 && out_bytes < need)
+            return fail(EWALD_ENOMEM, "grid buffer of %lld bytes below the %lld the plan's grid needs",
+                        (long long)out_bytes, (long long)need);
+    }
     if (st) {
         if (!plan) return fail(EWALD_EINVAL, "null plan");
         if (!reinterpret_cast<const Plan*>(plan)->stresslet)
@@ -630,6 +639,10 @@ int run(ewald_plan_t plan, int64_t n64, const double* x, const double* f, void* 
     };
     mark(0);
     if ((e = launch_sort(*pl, w, n, x, f, s)) != hipSuccess) return hip_fail(e, "sort");
+    if (what == Out::CountPairs) {
+        e = launch_count_pairs(*pl, w, n, (unsigned long long*)o1, s);
+        return e == hipSuccess ? EWALD_OK : hip_fail(e, "pair count");
+    }
     if (st && (e = launch_gather_st(*pl, w, n, q, nrm, s)) != hipSuccess) return hip_fail(e, "stresslet gather");
     mark(1);
     if (what == Out::Full || what == Out::Parts) {
@@ -638,7 +651,7 @@ int run(ewald_plan_t plan, int64_t n64, const double* x, const double* f, void* 
     mark(2);
     if ((e = launch_p2g(*pl, w, n, s, st)) != hipSuccess) return hip_fail(e, "P2G");
     mark(3);
-    const size_t gbytes = (size_t)3 * pl->g.ncells * (pl->grid64 ? 8 : 4);
+    const size_t gbytes = (size_t)pl->info.grid_bytes;
     if (what == Out::Spread) {
         e = hipMemcpyAsync(o1, w.grid, gbytes, hipMemcpyDeviceToDevice, s);
         return e == hipSuccess ? EWALD_OK : hip_fail(e, "grid copy");
@@ -752,16 +765,30 @@ int ewald_eval_combined_parts(ewald_plan_t plan, int64_t n, const double* x, con
     return run(plan, n, x, f, u_near, u_far, workspace, workspace_bytes, stream, Out::Parts, true, q, nrm);
 }
 
-int ewald_spread(ewald_plan_t plan, int64_t n, const double* x, const double* f, void* grid, void* workspace,
-                 int64_t workspace_bytes, void* stream)
+int ewald_spread(ewald_plan_t plan, int64_t n, const double* x, const double* f, void* grid, int64_t grid_bytes,
+                 void* workspace, int64_t workspace_bytes, void* stream)
 {
-    return run(plan, n, x, f, grid, grid, workspace, workspace_bytes, stream, Out::Spread);
+    return run(plan, n, x, f, grid, grid, workspace, workspace_bytes, stream, Out::Spread, false, nullptr, nullptr,
+               grid_bytes);
 }
 
 int ewald_far_grid(ewald_plan_t plan, int64_t n, const double* x, const double* f, void* grid,
-                   void* workspace, int64_t workspace_bytes, void* stream)
+                   int64_t grid_bytes, void* workspace, int64_t workspace_bytes, void* stream)
 {
-    return run(plan, n, x, f, grid, grid, workspace, workspace_bytes, stream, Out::FarGrid);
+    return run(plan, n, x, f, grid, grid, workspace, workspace_bytes, stream, Out::FarGrid, false, nullptr, nullptr,
+               grid_bytes);
+}
+
+int ewald_count_pairs(ewald_plan_t plan, int64_t n, const double* x, const double* f, uint64_t* count,
+                      void* workspace, int64_t workspace_bytes, void* stream)
+{
+    if (n == 0 && count && plan) {
+        Work w{};
+        const hipError_t e = launch_count_pairs(*reinterpret_cast<Plan*>(plan), w, 0, (unsigned long long*)count,
+                                                (hipStream_t)stream);
+        return e == hipSuccess ? EWALD_OK : hip_fail(e, "count reset");
+    }
+    return run(plan, n, x, f, count, count, workspace, workspace_bytes, stream, Out::CountPairs);
 }
 
 int ewald_stage_ms(ewald_plan_t plan, float* ms, int32_t count)

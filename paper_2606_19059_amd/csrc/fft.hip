@@ -16,7 +16,7 @@
 // autosort FFT held in LDS, one workgroup per batch of adjacent columns (adjacent in
 // memory, so every row of a batch is one contiguous read).  Twiddles come from FP64 host
 // tables.  The k = 0 mode and the Nyquist planes are set to zero; the half-spectrum
-// convolution is enough because every field involved is real (Sec. 3.5).  The global
+// convolution is enough because every field involved is real (Sec. 3.4).  The global
 // scale h1 h2 h3 / (M1 M2 M3) of the DFT round trip and of eq. (g2p) is folded into the
 // CNV tables, so the inverse transforms are unnormalised.
 #include "internal.h"
@@ -284,7 +284,7 @@ __global__ __launch_bounds__(256) void k_fft_x_cnv(T* __restrict__ grid, int64_t
 // ---- pass 3 for combined single and double layer sources ----
 // The 9 components (force 0-2, symmetric stresslet tensor 3-8: xx, yy, zz, xy, xz, yz) have
 // been transformed along x (k_fft_x_cnv without CNV).  Per x-column batch: CNV 9 -> 3 in
-// FP64 (Sec. 2.2, combined layers),
+// FP64 (Sec. 2.3, combined layers),
 //   vhat_a = A(k) [ (k^2 phi_a - k_a (k.phi)) + i (k^2 (k_a tr S + 2 (S k)_a) - 2 k_a (k.S k)) ],
 // the first term Ghat^F, the second That^F of the stresslet (That_abc = (8 pi i / k^4)
 // (k^2 (delta_bc k_a + delta_ab k_c + delta_ac k_b) - 2 k_a k_b k_c), contracted with the

@@ -100,6 +100,7 @@ struct Work {
     int* start;      // [ncells+1] exclusive scan of count
     int* chunk_off;  // [ntiles+1] P2P wave work-list offsets
     int* part;       // scan partials
+    int* cell_lists; // [cell_list_elems(n)] cells too large for a one-thread sort of their order
     void* rec;       // [n] Rec64, sorted order
     double* u_near;  // [3][n] near field, sorted order
     double* srec;    // [n][6] symmetric stresslet tensors (xx, yy, zz, xy, xz, yz), sorted order
@@ -123,6 +124,8 @@ hipError_t launch_sort(const Plan& pl, const Work& w, int n, const double* x, co
 hipError_t launch_gather_st(const Plan& pl, const Work& w, int n, const double* q, const double* nrm,
                             hipStream_t s);
 hipError_t launch_p2p(const Plan& pl, const Work& w, int n, hipStream_t s, bool st);
+// exact number of ordered pairs (i != j, all images) with 0 < |r| < r_c, written to *count
+hipError_t launch_count_pairs(const Plan& pl, const Work& w, int n, unsigned long long* count, hipStream_t s);
 hipError_t launch_p2g(const Plan& pl, const Work& w, int n, hipStream_t s, bool st);
 hipError_t launch_fgc(const Plan& pl, const Work& w, hipStream_t s, bool inverse_too, bool cnv, bool st);
 hipError_t launch_g2p(const Plan& pl, const Work& w, int n, const double* f, double* u,
@@ -133,5 +136,7 @@ hipError_t launch_fill_i32(int* p, int64_t count, int value, hipStream_t s);
 // needs scan_part_elems(count) ints.
 hipError_t launch_exclusive_scan(const int* in, int* out, int count, int* part, hipStream_t s);
 int scan_part_elems(int count);
+// ints of the sort's lists of large cells for n particles
+int64_t cell_list_elems(int64_t n);
 
 }  // namespace ewald

@@ -186,7 +186,7 @@ struct Coef<float, Fast> {
     __device__ static inline void eval(double r2, const PairArgs& a, float& a1, float& b) { coef32(r2, a, a1, b); }
 };
 
-// Stresslet pair (combined single and double layer sources, Sec. 2.2): with the screened
+// Stresslet pair (combined single and double layer sources, Sec. 2.3): with the screened
 // remainder of T(r) = -6 r r r / |r|^5,
 //   T^N_abc(r) S_bc = alpha r_a (r.S r) + beta (2 (S r)_a + tr(S) r_a)   (S symmetric),
 //   alpha = -2 |r|^-3 (3 erfc(xi |r|) |r|^-2 + e^{-xi^2 r^2} (6 xi/(sqrt(pi) |r|) + 4 xi^3 |r|/sqrt(pi))),
@@ -275,11 +275,15 @@ constexpr int kTest = 32;    // sources tested per round (queue <= kTest * 64 pa
 
 // TF: precision of the pair formula and of the staged forces; TA: accumulator precision.
 // Positions and the r^2 < r_c^2 test are FP64 in both modes (same VALU rate as FP32).
-template <typename TF, typename TA, bool Fast>
+// Count: no pair formula; the wave only counts its accepted (target, source) pairs and adds
+// the count to *pair_count (one integer atomic per wave): the exact number of ordered pairs
+// the near-field sum runs over, for measurement.
+template <typename TF, typename TA, bool Fast, bool Count = false>
 __global__ __launch_bounds__(64) void k_p2p(int n, const Rec64* __restrict__ rec,
                                             const int* __restrict__ start,
                                             const int* __restrict__ chunk_off, Geometry g,
-                                            PairArgs a, double* __restrict__ u_near)
+                                            PairArgs a, double* __restrict__ u_near,
+                                            unsigned long long* __restrict__ pair_count = nullptr)
 {
     __shared__ double tgt[3][kWave];
     __shared__ TA acc[3][kWave];
@@ -322,6 +326,7 @@ __global__ __launch_bounds__(64) void k_p2p(int n, const Rec64* __restrict__ rec
     __syncthreads();
 
     int rhead = 0, rcount = 0;
+    unsigned long long counted = 0;
 
     // test the targets against ring sources [rhead, rhead + cnt), then drain the queue
     auto process = [&](int cnt) {
@@ -332,8 +337,13 @@ __global__ __launch_bounds__(64) void k_p2p(int n, const Rec64* __restrict__ rec
             const double r2 = rx * rx + ry * ry + rz * rz;
             const bool pass = (r2 < a.rc2) && (r2 > 0.0);
             const unsigned long long b = __ballot(pass);
-            if (pass) queue[qn + lanes_below(b)] = (unsigned short)(lane | (j << 6));
+            if (!Count && pass) queue[qn + lanes_below(b)] = (unsigned short)(lane | (j << 6));
             qn += __popcll(b);
+        }
+        if (Count) {
+            counted += (unsigned long long)qn;
+            __syncthreads();
+            return;
         }
         __syncthreads();
         for (int q0 = 0; q0 < qn; q0 += kWave) {
@@ -422,6 +432,10 @@ __global__ __launch_bounds__(64) void k_p2p(int n, const Rec64* __restrict__ rec
         process(c);
         rhead = (rhead + c) & (kRing - 1);
         rcount -= c;
+    }
+    if (Count) {
+        if (lane == 0 && counted > 0) atomicAdd(pair_count, counted);
+        return;
     }
     if (active) {
         u_near[i] = (double)acc[0][lane];
@@ -794,9 +808,10 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
 
 }  // namespace
 
-hipError_t launch_p2p(const Plan& pl, const Work& w, int n, hipStream_t s, bool st)
+namespace {
+
+PairArgs pair_args(const Plan& pl)
 {
-    if (n <= 0) return hipSuccess;
     PairArgs a;
     a.xi = pl.xi;
     a.xi2 = pl.xi * pl.xi;
@@ -813,6 +828,29 @@ hipError_t launch_p2p(const Plan& pl, const Work& w, int n, hipStream_t s, bool 
         a.ec[k] = 1.0 / fact;
         fact *= (double)(k + 1);
     }
+    return a;
+}
+
+__global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
+
+}  // namespace
+
+hipError_t launch_count_pairs(const Plan& pl, const Work& w, int n, unsigned long long* count, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, count);
+    if (n > 0) {
+        const PairArgs a = pair_args(pl);
+        const int64_t waves = (int64_t)pl.g.ntiles + (n + kWave - 1) / kWave;
+        hipLaunchKernelGGL((k_p2p<double, double, false, true>), dim3((unsigned)waves), dim3(kWave), 0, s, n,
+                           (const Rec64*)w.rec, w.start, w.chunk_off, pl.g, a, nullptr, count);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_p2p(const Plan& pl, const Work& w, int n, hipStream_t s, bool st)
+{
+    if (n <= 0) return hipSuccess;
+    const PairArgs a = pair_args(pl);
     const bool fast = pl.p.tol >= 1e-10;
     const int64_t waves = (int64_t)pl.g.ntiles + (n + kWave - 1) / kWave;
     const dim3 grid((unsigned)waves), block(kWave);

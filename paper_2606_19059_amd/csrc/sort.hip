@@ -3,6 +3,9 @@
 // one compact CSR list keyed by grid cell serves both, since P2P cells are unions of grid
 // cells).  Integer atomics touch only the per-cell counters; the order inside a cell is
 // made deterministic by sorting it by original index.
+#include <algorithm>
+#include <climits>
+
 #include "internal.h"
 
 namespace ewald {
@@ -64,15 +67,37 @@ __global__ void k_scatter(int n, const int* __restrict__ key, int* __restrict__ 
     perm[slot] = i;
 }
 
-// Order each cell's particles by original index (insertion sort; cells of the sizes
-// seen here hold a few to a few hundred particles).  Cells above `cap` keep the
-// scatter order: still correct, only not bitwise reproducible.
-__global__ void k_cell_order(int ncells, const int* __restrict__ start, int* __restrict__ perm, int cap)
+// Order each cell's particles by original index, so that the sorted order (and every sum
+// taken in it) does not depend on the order of the scatter's atomics.  Cells of up to
+// kCellSerial particles are sorted here by one thread (insertion sort); larger ones are
+// appended to one of two lists (`lists[0]`, `lists[1]` hold their lengths) and sorted by
+// k_sort_mid_cells (one wavefront per cell, up to kCellMid particles) or k_sort_big_cells
+// (one block per cell, any size).  The lists' order varies, but each cell's result does not.
+constexpr int kCellSerial = 16;
+constexpr int kCellMid = 256;
+constexpr int kBigThreads = 256;
+constexpr int kBigRun = 8192;  // ints sorted in LDS at once (32 KB)
+
+__host__ __device__ inline int64_t mid_list_cap(int64_t n) { return n / (kCellSerial + 1) + 1; }
+__host__ __device__ inline int64_t big_list_cap(int64_t n) { return n / (kCellMid + 1) + 1; }
+
+__global__ void k_cell_order(int ncells, const int* __restrict__ start, int* __restrict__ perm,
+                             int* __restrict__ lists, int64_t mid_cap)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncells) return;
     const int a = start[c], b = start[c + 1];
-    if (b - a < 2 || b - a > cap) return;
+    if (b - a < 2) return;
+    if (b - a > kCellMid) {
+        const int k = atomicAdd(&lists[1], 1);
+        lists[2 + mid_cap + k] = c;
+        return;
+    }
+    if (b - a > kCellSerial) {
+        const int k = atomicAdd(&lists[0], 1);
+        lists[2 + k] = c;
+        return;
+    }
     for (int i = a + 1; i < b; ++i) {
         const int v = perm[i];
         int j = i - 1;
@@ -81,6 +106,123 @@ __global__ void k_cell_order(int ncells, const int* __restrict__ start, int* __r
             --j;
         }
         perm[j + 1] = v;
+    }
+}
+
+// One wavefront per listed cell (kCellSerial < size <= kCellMid): every lane holds up to
+// four of the cell's (distinct) indices, counts how many of the cell's indices are smaller
+// (a broadcast read of each from LDS) and writes its index at that rank.
+__global__ void __launch_bounds__(256) k_sort_mid_cells(const int* __restrict__ start, int* __restrict__ perm,
+                                                        const int* __restrict__ lists)
+{
+    constexpr int kPer = kCellMid / kWave;
+    __shared__ int sh[256 / kWave][kCellMid];
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    int* s = sh[wv];
+    const int nmid = lists[0];
+    const int waves = gridDim.x * (blockDim.x / kWave);
+    for (int q = blockIdx.x * (blockDim.x / kWave) + wv; q < nmid; q += waves) {
+        const int c = lists[2 + q];
+        const int a = start[c], m = start[c + 1] - a;
+        int v[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int i = lane + k * kWave;
+            v[k] = i < m ? perm[a + i] : 0;
+            if (i < m) s[i] = v[k];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        int rank[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) rank[k] = 0;
+        for (int t = 0; t < m; ++t) {
+            const int o = s[t];
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) rank[k] += (o < v[k]) ? 1 : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kPer; ++k)
+            if (lane + k * kWave < m) perm[a + rank[k]] = v[k];
+        // the next cell overwrites this wave's LDS row
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+// number of entries of the ascending, distinct a[0..len) below v
+__device__ inline int count_below(const int* __restrict__ a, int len, int v)
+{
+    int lo = 0, hi = len;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// One block per listed cell (size > kCellMid): runs of kBigRun indices are sorted in LDS
+// (bitonic network, padded to a power of two), then merged pairwise, each index placed at
+// its rank in the merged run (its offset in its own run plus the count of smaller indices
+// in the other, by binary search), ping-ponging between the cell's range of `perm` and
+// the same range of `scratch`.
+__global__ void __launch_bounds__(kBigThreads) k_sort_big_cells(const int* __restrict__ start, int* __restrict__ perm,
+                                                                int* __restrict__ scratch, const int* __restrict__ lists,
+                                                                int64_t mid_cap)
+{
+    __shared__ int s[kBigRun];
+    const int nbig = lists[1];
+    const int tid = threadIdx.x;
+    for (int q = blockIdx.x; q < nbig; q += gridDim.x) {
+        const int c = lists[2 + mid_cap + q];
+        const int a = start[c], m = start[c + 1] - a;
+        int* v = perm + a;
+        for (int r0 = 0; r0 < m; r0 += kBigRun) {
+            const int len = min(kBigRun, m - r0);
+            int p2 = 1;
+            while (p2 < len) p2 <<= 1;
+            for (int i = tid; i < p2; i += kBigThreads) s[i] = i < len ? v[r0 + i] : INT_MAX;
+            __syncthreads();
+            for (int k = 2; k <= p2; k <<= 1)
+                for (int j = k >> 1; j > 0; j >>= 1) {
+                    for (int i = tid; i < p2; i += kBigThreads) {
+                        const int l = i ^ j;
+                        if (l > i) {
+                            const int x = s[i], y = s[l];
+                            if ((x > y) == ((i & k) == 0)) {
+                                s[i] = y;
+                                s[l] = x;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+            for (int i = tid; i < len; i += kBigThreads) v[r0 + i] = s[i];
+            __syncthreads();
+        }
+        int* src = v;
+        int* dst = scratch + a;
+        for (int w = kBigRun; w < m; w *= 2) {
+            for (int i = tid; i < m; i += kBigThreads) {
+                const int lo = (i / (2 * w)) * (2 * w);
+                const int mid = min(lo + w, m), hi = min(lo + 2 * w, m);
+                const int val = src[i];
+                const int pos = (i < mid) ? (i - lo) + count_below(src + mid, hi - mid, val)
+                                          : (i - mid) + count_below(src + lo, mid - lo, val);
+                dst[lo + pos] = val;
+            }
+            __syncthreads();
+            int* t = src;
+            src = dst;
+            dst = t;
+        }
+        if (src != v) {
+            for (int i = tid; i < m; i += kBigThreads) v[i] = src[i];
+        }
+        __syncthreads();
     }
 }
 
@@ -221,6 +363,8 @@ inline int blocks_for(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
 int scan_part_elems(int count) { return (count + kScanChunk - 1) / kScanChunk + 1; }
 
+int64_t cell_list_elems(int64_t n) { return 2 + mid_list_cap(n) + big_list_cap(n); }
+
 hipError_t launch_fill_i32(int* p, int64_t count, int value, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
@@ -251,8 +395,17 @@ hipError_t launch_sort(const Plan& pl, const Work& w, int n, const double* x, co
     hipLaunchKernelGGL(k_copy_i32, dim3(blocks_for(g.ncells, 256)), dim3(256), 0, s, w.start, w.count,
                        g.ncells);
     hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, w.key, w.count, w.perm);
+    // per-cell order by original index; the key array is free after the scatter and serves as
+    // the merge buffer of the largest cells
+    if ((e = launch_fill_i32(w.cell_lists, 2, 0, s)) != hipSuccess) return e;
+    const int64_t mid_cap = mid_list_cap(n);
     hipLaunchKernelGGL(k_cell_order, dim3(blocks_for(g.ncells, 256)), dim3(256), 0, s, g.ncells, w.start,
-                       w.perm, 512);
+                       w.perm, w.cell_lists, mid_cap);
+    const int mid_blocks = (int)std::min<int64_t>(2048, std::max<int64_t>(1, mid_list_cap(n) / 4));
+    hipLaunchKernelGGL(k_sort_mid_cells, dim3(mid_blocks), dim3(256), 0, s, w.start, w.perm, w.cell_lists);
+    const int big_blocks = (int)std::min<int64_t>(512, big_list_cap(n));
+    hipLaunchKernelGGL(k_sort_big_cells, dim3(big_blocks), dim3(kBigThreads), 0, s, w.start, w.perm, w.key,
+                       w.cell_lists, mid_cap);
     hipLaunchKernelGGL(k_gather64, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, x, f, w.perm, g,
                        (Rec64*)w.rec);
     // P2P work list: waves per tile, then their offsets

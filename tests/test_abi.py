@@ -61,7 +61,7 @@ def _EF(xi, h):  # eq. (ese), Fourier term
 
 @pytest.mark.parametrize("tol", [1e-4, 1e-6, 1e-8, 1e-10])
 def test_parameters_follow_error_split(tol):
-    """xi and r_c put E^N and E^F at tol/3 (Sec. 2.3 split), window error <= tol/3."""
+    """xi and r_c put E^N and E^F at tol/3 (Sec. 2.4 split), window error <= tol/3."""
     i = E.resolve((1, 1, 1), tol, grid=(64, 64, 64))
     h = 1.0 / 64
     assert _EF(i["xi"], h) == pytest.approx(tol / 3, rel=1e-6)
@@ -141,3 +141,19 @@ def test_stresslet_plans():
     with pytest.raises(E.EwaldError) as ei:
         E.resolve((1, 1, 1), 1e-6, grid=g, n_max=1000, stresslet=True, deterministic=True)
     assert ei.value.code == E.EWALD_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("precision,tol,grid,elem", [("fp64", 1e-8, (32, 32, 64), 8), ("fp32", 1e-5, (64, 64, 128), 4),
+                                                     ("fp32", 1e-7, (32, 32, 64), 8)])
+def test_info_self_coefficient_and_grid_bytes(precision, tol, grid, elem):
+    """The plan reports the self-term coefficient (equal to the oracle's self term per unit
+    force) and the byte size of the diagnostic grids (element type by fourier_fp64)."""
+    import numpy as np
+
+    import oracle
+
+    info = E.resolve((1.0, 1.0, 2.0), tol, precision=precision, grid=grid, n_max=1000)
+    f = np.ones((3, 1))
+    assert info["self_coef"] == pytest.approx(-oracle.self_term(f, info["xi"])[0, 0], rel=1e-15)
+    assert info["fourier_fp64"] == (elem == 8)
+    assert info["grid_bytes"] == 3 * grid[0] * grid[1] * grid[2] * elem

@@ -1,9 +1,14 @@
-"""Parity at the benchmark's full size, in the configuration bench.py times.
+"""Parity at the benchmark configurations' full sizes, in the launch configuration bench.py
+times (the same plans: the large-problem P2P launch, the P2G segment split and the G2P
+grouping only occur at these sizes).
 
-N = 1e6 uniform particles, tol 1e-8, 128^3 grid, FP64: the oracle evaluates sampled
-targets one by one (all N sources).  The P2P stage is compared at the same xi, r_c within
-the bound of the plan's pair formula (1e-10; the reduced-cost formula of tol >= 1e-10), and
-the full result within tol.
+The oracle evaluates sampled targets one by one with all N sources: 1024 targets for c2,
+c4 and H, 256 for c3 (ten million sources).  Besides seeded random targets, the sample
+holds the particles nearest the periodic seam (a coordinate near 0 or L) and nearest the
+faces of the P2P tiles, where neighbour-tile and image handling matter most.  At those
+targets the near field is compared with the oracle's real-space sum at the plan's xi and
+r_c (within the bound of the plan's pair formula) and the whole result with the classical
+Ewald sum (within tol).
 """
 import numpy as np
 import pytest
@@ -14,69 +19,99 @@ from paper_2606_19059_amd import workloads as W
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
+# near-field bound of each plan's pair formula (max-norm, relative to the array's max)
+NEAR_BOUND = {"fp64_full": 1e-12, "fp64_fast": 1e-10, "fp32": 2e-6}
 
-@pytest.fixture(scope="module")
-def c2():
+
+def edge_targets(x, box, tile_edge, count, seed, k_edge):
+    """`count` distinct targets: the k_edge particles nearest the periodic seam, the k_edge
+    nearest a P2P tile face (not on the seam), the rest seeded random."""
+    L = np.asarray(box, dtype=np.float64).reshape(3, 1)
+    w = oracle.wrap(x, L)
+    seam = np.min(np.minimum(w, L - w), axis=0)
+    e = np.asarray(tile_edge, dtype=np.float64).reshape(3, 1)
+    r = np.mod(w, e)
+    face = np.min(np.minimum(r, e - r), axis=0)
+    face = np.where(seam < 0.5 * np.min(e), np.inf, face)
+    picked = list(np.argsort(seam, kind="stable")[:k_edge]) + list(np.argsort(face, kind="stable")[:k_edge])
+    rest = W.sample_targets(x.shape[1], count, seed)
+    out = list(dict.fromkeys(picked))
+    for t in rest:
+        if len(out) >= count:
+            break
+        if t not in set(out):
+            out.append(int(t))
+    return np.sort(np.asarray(out[:count], dtype=np.int64))
+
+
+def check_config(E, name, precision, n_targets, k_edge, tol=None, P=None):
+    wl = W.WORKLOADS[name]
+    x, f = wl.make()
+    X, F = torch.from_numpy(x).to("cuda"), torch.from_numpy(f).to("cuda")
+    tol = tol or wl.tol
+    plan = E.Plan(wl.box, tol, grid=wl.grid, P=P, n_max=wl.n, precision=precision)
+    info = plan.info
+    u = plan.eval(X, F)
+    un, uf = plan.eval_parts(X, F)
+    torch.cuda.synchronize()
+    u, un, uf = u.cpu().numpy(), un.cpu().numpy(), uf.cpu().numpy()
+    h = np.array(info["h"])
+    tgt = edge_targets(x, wl.box, info["tile"] * h, n_targets, 100 + (int(name[1:]) if name[1:].isdigit() else 11),
+                       k_edge)
+    rn = oracle.real_space(x, f, wl.box, info["xi"], info["r_c"], targets=tgt)
+    kind = "fp32" if precision == "fp32" else ("fp64_fast" if tol >= 1e-10 else "fp64_full")
+    near_err = np.max(np.abs(un[:, tgt] - rn)) / np.max(np.abs(rn))
+    ref = oracle.ewald_sum(x, f, wl.box, targets=tgt)
+    err = oracle.rel_err(u[:, tgt], ref)
+    print("%s %s: P=%d, %d targets (%d seam + %d tile-face): near-field max rel err %.2e (bound %g), "
+          "sampled rel err %.3e (tol %g)" % (name, precision, info["P"], len(tgt), k_edge, k_edge, near_err,
+                                              NEAR_BOUND[kind], err, tol))
+    assert near_err < NEAR_BOUND[kind]
+    # eval and eval_parts agree: u = u_near + u_far - c f with the library's self coefficient
+    us = un + uf - info["self_coef"] * f
+    assert np.max(np.abs(us - u)) < 1e-12 * np.max(np.abs(u))
+    return wl, x, f, X, F, u, err, tol
+
+
+def test_c2_full_size_meets_tolerance():
+    import paper_2606_19059_amd as E
+
+    _, _, _, _, _, _, err, tol = check_config(E, "c2", "fp64", 1024, 64)
+    assert err <= tol
+
+
+def test_c2_configured_window_error_is_reported():
+    """At the configured P = 12 the Gaussian window limits the error to ~1e-7."""
     import paper_2606_19059_amd as E
 
     wl = W.WORKLOADS["c2"]
     x, f = wl.make()
-    X = torch.from_numpy(x).to("cuda")
-    F = torch.from_numpy(f).to("cuda")
-    return E, wl, x, f, X, F
-
-
-def test_c2_full_size_meets_tolerance(c2):
-    E, wl, x, f, X, F = c2
-    plan = E.Plan(wl.box, wl.tol, grid=wl.grid, n_max=wl.n)
-    un, uf = plan.eval_parts(X, F)
-    u = plan.eval(X, F)
-    torch.cuda.synchronize()
-    tgt = W.sample_targets(wl.n, 16, seed=102)
-    u_np, un_np = u.cpu().numpy(), un.cpu().numpy()
-    # P2P stage: the oracle's real-space sum at the plan's xi and r_c
-    rn = oracle.real_space(x, f, wl.box, plan.info["xi"], plan.info["r_c"], targets=tgt)
-    assert np.max(np.abs(un_np[:, tgt] - rn)) < 1e-10 * np.max(np.abs(rn))
-    # the whole evaluation against the classical Ewald sum
-    ref = oracle.ewald_sum(x, f, wl.box, targets=tgt)
-    err = oracle.rel_err(u_np[:, tgt], ref)
-    print("c2: P=%d sampled relative error %.3e (tol %g)" % (plan.info["P"], err, wl.tol))
-    assert err <= wl.tol
-    # eval and eval_parts agree
-    us = un_np + uf.cpu().numpy() - plan.self_coef * f
-    assert np.max(np.abs(us - u_np)) < 1e-12 * np.max(np.abs(u_np))
-
-
-def test_c2_configured_window_error_is_reported(c2):
-    """At the configured P = 12 the Gaussian window limits the error to ~1e-7."""
-    E, wl, x, f, X, F = c2
     plan = E.Plan(wl.box, wl.tol, grid=wl.grid, P=wl.P, n_max=wl.n)
-    u = plan.eval(X, F).cpu().numpy()
-    tgt = W.sample_targets(wl.n, 16, seed=102)
+    u = plan.eval(torch.from_numpy(x).to("cuda"), torch.from_numpy(f).to("cuda")).cpu().numpy()
+    tgt = W.sample_targets(wl.n, 64, seed=102)
     err = oracle.rel_err(u[:, tgt], oracle.ewald_sum(x, f, wl.box, targets=tgt))
     print("c2 at P=12: sampled relative error %.3e (window model %.2e)" % (err, plan.info["err_window"]))
     assert err < 10 * plan.info["err_window"]
 
 
-@pytest.mark.parametrize("name", ["c3", "c4", "H"])
-def test_fp32_configs_full_size(name):
-    """FP32 bulk at full size: sampled error within tol, and against the FP64 GPU path."""
+@pytest.mark.parametrize("name,n_targets,k_edge", [("H", 1024, 64), ("c4", 1024, 64), ("c3", 256, 32)])
+def test_fp32_configs_full_size(name, n_targets, k_edge):
+    """FP32 bulk at full size: near field and sampled error against the oracle, and the whole
+    N against the FP64 GPU path at a tighter tolerance on the same grid."""
     import paper_2606_19059_amd as E
 
-    wl = W.WORKLOADS[name]
-    x, f = wl.make()
-    X = torch.from_numpy(x).to("cuda")
-    F = torch.from_numpy(f).to("cuda")
-    p32 = E.Plan(wl.box, wl.tol, grid=wl.grid, n_max=wl.n, precision="fp32")
-    u32 = p32.eval(X, F).cpu().numpy()
-    tgt = W.sample_targets(wl.n, 12, seed=100 + int(name[1:]) if name[1:].isdigit() else 111)
-    ref = oracle.ewald_sum(x, f, wl.box, targets=tgt)
-    err = oracle.rel_err(u32[:, tgt], ref)
-    # the FP64 path at a tighter tolerance on the same grid, all N
+    wl, x, f, X, F, u32, err, tol = check_config(E, name, "fp32", n_targets, k_edge)
+    assert err <= tol
     p64 = E.Plan(wl.box, min(wl.tol, 1e-8), grid=wl.grid, n_max=wl.n, precision="fp64")
     u64 = p64.eval(X, F).cpu().numpy()
     err_full = oracle.rel_err(u32, u64)
-    print("%s: fp32 P=%d sampled err %.3e, full-N err vs FP64 path %.3e (tol %g)"
-          % (name, p32.info["P"], err, err_full, wl.tol))
-    assert err <= wl.tol
+    print("%s: full-N err vs FP64 path %.3e (tol %g)" % (name, err_full, wl.tol))
     assert err_full <= wl.tol
+
+
+def test_h_fp64_full_size_meets_tolerance():
+    """The 1e-6 headline in the plain FP64 mode (the FP32-bulk mode's comparison point)."""
+    import paper_2606_19059_amd as E
+
+    _, _, _, _, _, _, err, tol = check_config(E, "H", "fp64", 1024, 64)
+    assert err <= tol

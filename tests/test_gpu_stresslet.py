@@ -1,4 +1,4 @@
-"""Combined single and double layer sources (Stokeslet + stresslet, Sec. 2.2) on the GPU.
+"""Combined single and double layer sources (Stokeslet + stresslet, Sec. 2.3) on the GPU.
 
 Stage parity against the spectral oracle (element by element, 1e-12 / 1e-11 relative to the
 array's max, plans with tol < 1e-10 so the full-precision pair formula runs), the whole sum

@@ -377,3 +377,32 @@ def test_spectral_combined_far_field_converges_to_direct_fourier_sum(window):
                                                                window=window), ref))
     assert errs[0] > errs[1] > errs[2]
     assert errs[2] < (1e-11 if window == "kb" else 1e-8)
+
+
+# ---------------------------------------------------------------- error metrics
+
+
+def test_rel_err_hand_computed():
+    """Relative RMS error over all components: ||u - r||_2 / ||r||_2, by hand.
+
+    r = [[3, 0], [0, 4]] has norm 5; u - r = [[0, 1], [-2, 2]] has norm 3, so 3/5.  A
+    metric that averaged per component, used the max norm, or divided by ||u|| fails.
+    """
+    r = np.array([[3.0, 0.0], [0.0, 4.0]])
+    u = np.array([[3.0, 1.0], [-2.0, 6.0]])
+    assert oracle.rel_err(u, r) == pytest.approx(0.6, rel=1e-15)
+    # symmetric in nothing: the reference's norm is the denominator
+    assert oracle.rel_err(r, u) == pytest.approx(3.0 / math.sqrt(9 + 1 + 4 + 36), rel=1e-15)
+    assert oracle.rel_err(r, r) == 0.0
+    # zero reference: the absolute norm
+    assert oracle.rel_err(np.array([[3.0], [4.0]]), np.zeros((2, 1))) == pytest.approx(5.0)
+
+
+def test_max_rel_err_hand_computed():
+    """max |u - r| / max |r| over all entries, by hand: max |u - r| = 2 (entry [1, 0]),
+    max |r| = 4, so 0.5 (an RMS or per-entry relative metric gives another value)."""
+    r = np.array([[3.0, 0.0], [-1.0, 4.0]])
+    u = np.array([[3.5, 0.0], [1.0, 4.0]])
+    assert oracle.max_rel_err(u, r) == pytest.approx(0.5, rel=1e-15)
+    assert oracle.max_rel_err(r, r) == 0.0
+    assert oracle.max_rel_err(np.array([[-7.0]]), np.zeros((1, 1))) == pytest.approx(7.0)
