@@ -79,10 +79,15 @@ enum {
                                           evaluated once and its two contributions are added with
                                           atomics, so repeated evaluations agree to rounding
                                           (~1e-16 relative), not bitwise */
-    EWALD_FLAG_STRESSLET = 1 << 12     /* the plan also evaluates stresslet (double-layer) sources
+    EWALD_FLAG_STRESSLET = 1 << 12,    /* the plan also evaluates stresslet (double-layer) sources
                                           with ewald_eval_combined: its workspace holds the sorted
                                           source tensors and a 9-component grid.  Not combinable
                                           with EWALD_FLAG_DETERMINISTIC (EWALD_EUNSUPPORTED) */
+    EWALD_FLAG_CHECK_INPUTS = 1 << 13  /* debug mode: every evaluation first counts the
+                                          non-finite values of its inputs on the device and
+                                          returns EWALD_EINVAL, with nothing else enqueued, if
+                                          there are any.  The check waits for the stream (the
+                                          evaluation calls then synchronise) */
 };
 
 /*
@@ -231,6 +236,15 @@ int ewald_count_pairs(ewald_plan_t plan, int64_t n, const double* x, const doubl
  * values; returns the number written or a negative status.
  */
 int ewald_stage_ms(ewald_plan_t plan, float* ms, int32_t count);
+
+/*
+ * Failure injection for tests of error handling: the next `count` evaluation calls made on
+ * the calling thread (any ewald_eval* entry point, ewald_spread, ewald_far_grid,
+ * ewald_count_pairs) return EWALD_EHIP after their argument checks, with nothing enqueued,
+ * as a failed launch would.  count = 0 disarms.  Returns EWALD_OK, or EWALD_EINVAL for
+ * count < 0.
+ */
+int ewald_debug_fail_next(int32_t count);
 
 /* Message describing the last failure on the calling thread ("" if none). */
 const char* ewald_last_error(void);

@@ -26,6 +26,7 @@ EWALD_FLAG_STAGE_TIMERS = 1 << 9
 EWALD_FLAG_WINDOW_KB = 1 << 10
 EWALD_FLAG_DETERMINISTIC = 1 << 11
 EWALD_FLAG_STRESSLET = 1 << 12
+EWALD_FLAG_CHECK_INPUTS = 1 << 13
 
 STAGES = ("sort", "p2p", "p2g", "fgc", "g2p", "total")
 
@@ -44,6 +45,7 @@ EXPORTS = (
     "ewald_far_grid",
     "ewald_count_pairs",
     "ewald_stage_ms",
+    "ewald_debug_fail_next",
     "ewald_last_error",
     "ewald_version",
 )
@@ -119,6 +121,7 @@ def load(path: str | None = None):
         getattr(lib, name).argtypes = [vp, i64, vp, vp, vp, i64, vp, i64, vp]
     lib.ewald_count_pairs.argtypes = [vp, i64, vp, vp, vp, vp, i64, vp]
     lib.ewald_stage_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32]
+    lib.ewald_debug_fail_next.argtypes = [i32]
     lib.ewald_last_error.restype = ctypes.c_char_p
     lib.ewald_version.restype = ctypes.c_char_p
     if path is None:
@@ -158,7 +161,7 @@ def _check_particles(x, f):
 
 def make_params(box, tol, xi=None, r_c=None, grid=None, P=None, precision="fp64", n_max=1 << 20,
                 window_shape=None, p2p_fp64_acc=False, timers=False, window="gaussian", deterministic=False,
-                stresslet=False):
+                stresslet=False, check_inputs=False):
     """The ewald_params struct for these arguments (None = derive from tol)."""
     p = Params()
     for d in range(3):
@@ -173,7 +176,8 @@ def make_params(box, tol, xi=None, r_c=None, grid=None, P=None, precision="fp64"
         raise ValueError("window must be 'gaussian' or 'kb'")
     p.precision = mode | (EWALD_FLAG_P2P_FP64_ACC if p2p_fp64_acc else 0) | (
         EWALD_FLAG_STAGE_TIMERS if timers else 0) | (EWALD_FLAG_WINDOW_KB if window == "kb" else 0) | (
-        EWALD_FLAG_DETERMINISTIC if deterministic else 0) | (EWALD_FLAG_STRESSLET if stresslet else 0)
+        EWALD_FLAG_DETERMINISTIC if deterministic else 0) | (EWALD_FLAG_STRESSLET if stresslet else 0) | (
+        EWALD_FLAG_CHECK_INPUTS if check_inputs else 0)
     p.reserved = 0
     p.n_max = int(n_max)
     p.window_shape = float(window_shape) if window_shape else 0.0
@@ -216,10 +220,10 @@ class Plan:
 
     def __init__(self, box, tol, xi=None, r_c=None, grid=None, P=None, precision="fp64", n_max=1 << 20,
                  window_shape=None, p2p_fp64_acc=False, timers=False, window="gaussian", deterministic=False,
-                 stresslet=False):
+                 stresslet=False, check_inputs=False):
         lib = load()
         p = make_params(box, tol, xi, r_c, grid, P, precision, n_max, window_shape, p2p_fp64_acc, timers,
-                        window, deterministic, stresslet)
+                        window, deterministic, stresslet, check_inputs)
         self._lib = lib  # kept so that the plan can be freed during interpreter shutdown
         h = ctypes.c_void_p()
         _check(lib.ewald_plan_create(ctypes.byref(p), ctypes.byref(h)))
@@ -350,6 +354,12 @@ class Plan:
         buf = (ctypes.c_float * len(STAGES))()
         k = _check(load().ewald_stage_ms(self._h, buf, len(STAGES)))
         return dict(zip(STAGES[:k], [float(v) for v in buf[:k]]))
+
+
+def debug_fail_next(count=1):
+    """Make the next `count` evaluation calls of this thread fail with EWALD_EHIP before
+    launching anything (tests of error handling)."""
+    _check(load().ewald_debug_fail_next(int(count)))
 
 
 def version():

@@ -24,6 +24,7 @@ using namespace ewald;
 namespace {
 
 thread_local std::string g_err;
+thread_local int g_fail_next = 0;  // evaluations left to fail (ewald_debug_fail_next)
 
 int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 int fail(int code, const char* fmt, ...)
@@ -333,7 +334,7 @@ int validate_and_resolve(const ewald_params* in, Plan* pl)
         return fail(EWALD_EINVAL, "unknown precision mode %d", mode);
     if (p.precision &
         ~(0xff | EWALD_FLAG_P2P_FP64_ACC | EWALD_FLAG_STAGE_TIMERS | EWALD_FLAG_WINDOW_KB | EWALD_FLAG_DETERMINISTIC |
-          EWALD_FLAG_STRESSLET))
+          EWALD_FLAG_STRESSLET | EWALD_FLAG_CHECK_INPUTS))
         return fail(EWALD_EINVAL, "unknown precision flags 0x%x", p.precision);
     if ((p.precision & EWALD_FLAG_STRESSLET) && (p.precision & EWALD_FLAG_DETERMINISTIC))
         return fail(EWALD_EUNSUPPORTED, "stresslet sources are evaluated by the symmetric P2P only "
@@ -430,6 +431,7 @@ int validate_and_resolve(const ewald_params* in, Plan* pl)
     pl->deterministic = (p.precision & EWALD_FLAG_DETERMINISTIC) != 0;
     pl->stresslet = (p.precision & EWALD_FLAG_STRESSLET) != 0;
     pl->timers = (p.precision & EWALD_FLAG_STAGE_TIMERS) != 0;
+    pl->check_inputs = (p.precision & EWALD_FLAG_CHECK_INPUTS) != 0;
     pl->P = p.P;
     pl->window_kb = kb;
     pl->m = p.window_shape;
@@ -629,9 +631,26 @@ int run(ewald_plan_t plan, int64_t n64, const double* x, const double* f, void* 
     }
     int rc = check_eval_args(plan, n64, x, f, o1, what == Out::Parts ? o2 : o1, ws, wsb, &w);
     if (rc != EWALD_OK || n64 == 0) return rc;
+    if (g_fail_next > 0) {
+        --g_fail_next;
+        return fail(EWALD_EHIP, "injected failure (ewald_debug_fail_next)");
+    }
     Plan* pl = reinterpret_cast<Plan*>(plan);
     hipStream_t s = (hipStream_t)stream;
     const int n = (int)n64;
+    if (pl->check_inputs) {
+        // debug mode: count the non-finite inputs into the workspace's scan partials, wait, refuse
+        hipError_t e = launch_count_nonfinite(x, 3 * n64, w.part, s);
+        if (e == hipSuccess) e = launch_count_nonfinite(f, 3 * n64, w.part + 1, s);
+        if (st && e == hipSuccess) e = launch_count_nonfinite(q, 3 * n64, w.part + 1, s, false);
+        if (st && e == hipSuccess) e = launch_count_nonfinite(nrm, 3 * n64, w.part + 1, s, false);
+        int h[2] = {0, 0};
+        if (e == hipSuccess) e = hipMemcpyAsync(h, w.part, sizeof h, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "input check");
+        if (h[0] + h[1] > 0)
+            return fail(EWALD_EINVAL, "inputs hold %d non-finite values (%d in x)", h[0] + h[1], h[0]);
+    }
     const bool t = pl->timers && what != Out::Spread && what != Out::FarGrid;
     hipError_t e;
     auto mark = [&](int k) {
@@ -807,6 +826,13 @@ int ewald_stage_ms(ewald_plan_t plan, float* ms, int32_t count)
     const int k = std::min<int>(count, kNumStages);
     for (int i = 0; i < k; ++i) ms[i] = v[i];
     return k;
+}
+
+int ewald_debug_fail_next(int32_t count)
+{
+    if (count < 0) return fail(EWALD_EINVAL, "count = %d < 0", count);
+    g_fail_next = count;
+    return EWALD_OK;
 }
 
 const char* ewald_last_error(void) { return g_err.c_str(); }

@@ -78,6 +78,7 @@ struct Plan {
     bool deterministic;    // bitwise reproducible P2P (one-sided pair evaluation)
     bool stresslet;        // workspace sized for combined Stokeslet + stresslet sources
     bool timers;
+    bool check_inputs;     // count non-finite inputs before evaluating (debug mode)
     int device;
     // device tables owned by the plan
     void* d_tables;        // one allocation holding everything below
@@ -131,6 +132,8 @@ hipError_t launch_fgc(const Plan& pl, const Work& w, hipStream_t s, bool inverse
 hipError_t launch_g2p(const Plan& pl, const Work& w, int n, const double* f, double* u,
                       double* u_near_out, double* u_far_out, hipStream_t s);
 hipError_t launch_fill_i32(int* p, int64_t count, int value, hipStream_t s);
+// *out (= 0 first when `reset`) += number of non-finite values among a[0..count)
+hipError_t launch_count_nonfinite(const double* a, int64_t count, int* out, hipStream_t s, bool reset = true);
 
 // Exclusive scan of in[0..count) into out[0..count] (out[count] = total); `part`
 // needs scan_part_elems(count) ints.

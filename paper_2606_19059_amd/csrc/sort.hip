@@ -374,6 +374,32 @@ hipError_t launch_fill_i32(int* p, int64_t count, int value, hipStream_t s)
     return hipGetLastError();
 }
 
+namespace {
+
+__global__ void k_count_nonfinite(const double* __restrict__ a, int64_t count, int* __restrict__ out)
+{
+    int bad = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+        bad += isfinite(a[i]) ? 0 : 1;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) bad += __shfl_xor(bad, o, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0 && bad) atomicAdd(out, bad);
+}
+
+}  // namespace
+
+hipError_t launch_count_nonfinite(const double* a, int64_t count, int* out, hipStream_t s, bool reset)
+{
+    if (reset) {
+        hipError_t e = launch_fill_i32(out, 1, 0, s);
+        if (e != hipSuccess) return e;
+    }
+    const int blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (count + 255) / 256));
+    hipLaunchKernelGGL(k_count_nonfinite, dim3(blocks), dim3(256), 0, s, a, count, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_exclusive_scan(const int* in, int* out, int count, int* part, hipStream_t s)
 {
     const int nb = (count + kScanChunk - 1) / kScanChunk;

@@ -371,3 +371,42 @@ def test_g2p_on_a_large_grid_with_clusters():
         err = maxrel(host(uf), ref)
         print("256^3 %s tol %g (FP64 grid: %s): far-field max rel err %.2e" % (prec, tol, pl.info["fourier_fp64"], err))
         assert err < bound
+
+
+# ---------------------------------------------------------------- failure handling
+
+
+def test_injected_failure_returns_ehip_before_launching():
+    """ewald_debug_fail_next: the next call fails with EWALD_EHIP and leaves the output as it
+    was (nothing enqueued); the call after it evaluates normally."""
+    E = _E()
+    pl = make_plan(E, "cube32_P8", 200)
+    x, f = W.particles(200, (1, 1, 1), seed=1)
+    X, F = dev(x), dev(f)
+    ref = host(pl.eval(X, F))
+    u = torch.full_like(X, 7.0)
+    E.debug_fail_next(1)
+    with pytest.raises(E.EwaldError) as ei:
+        pl.eval(X, F, out=u)
+    assert ei.value.code == E.EWALD_EHIP and "injected" in str(ei.value)
+    assert np.all(host(u) == 7.0)
+    assert np.max(np.abs(host(pl.eval(X, F)) - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_input_check_mode_refuses_non_finite_inputs():
+    """EWALD_FLAG_CHECK_INPUTS: non-finite positions or forces are refused with EWALD_EINVAL
+    and nothing else runs; finite inputs evaluate as without the flag."""
+    E = _E()
+    box, grid, xi, rc, P, m = CASES["cube32_P8"]
+    pl = make_plan(E, "cube32_P8", 300, check_inputs=True)
+    x, f = W.particles(300, box, seed=2)
+    ref = host(make_plan(E, "cube32_P8", 300).eval(dev(x), dev(f)))
+    assert np.max(np.abs(host(pl.eval(dev(x), dev(f))) - ref)) <= 1e-12 * np.max(np.abs(ref))
+    for arr, k, v in (("x", 5, np.nan), ("f", 17, np.inf), ("f", 299, -np.inf)):
+        xx, ff = x.copy(), f.copy()
+        (xx if arr == "x" else ff)[1, k] = v
+        u = torch.full((3, 300), 3.0, dtype=torch.float64, device="cuda")
+        with pytest.raises(E.EwaldError) as ei:
+            pl.eval(dev(xx), dev(ff), out=u)
+        assert ei.value.code == E.EWALD_EINVAL and "non-finite" in str(ei.value)
+        assert np.all(host(u) == 3.0)

@@ -1,4 +1,13 @@
-"""Serving: continuous admission of independent requests; each result equals its solo run."""
+"""Serving: continuous admission of independent requests out of one device arena.
+
+Each result equals the same request evaluated alone (1e-12 of its max: the symmetric P2P
+adds with atomics, so two runs agree to rounding only); admitted requests' evaluations
+overlap on the device clock; the server's device memory stays within its budget; requests
+that do not fit wait or pass a waiting larger one; malformed, expired and cancelled
+requests never reach the device.
+"""
+import math
+
 import numpy as np
 import pytest
 
@@ -9,10 +18,10 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def _stream(n_req, seed):
-    reqs = W.serving_stream(n_req, rate_per_s=2000.0, seed=seed, n_lo=1e3, n_hi=4e4)
+def _jobs(n_req, seed, n_lo=1e3, n_hi=4e4):
     from paper_2606_19059_amd import serve
 
+    reqs = W.serving_stream(n_req, rate_per_s=0.0, seed=seed, n_lo=n_lo, n_hi=n_hi)
     return serve.make_jobs(reqs)
 
 
@@ -27,52 +36,137 @@ def _solo(job):
 
 
 def test_results_equal_alone_and_in_the_mix():
+    """24 requests with N up to 1e6, all waiting at t = 0 on 4 slots: every result equals its
+    solo run, and the evaluations overlap on the device clock."""
     from paper_2606_19059_amd import serve
 
-    jobs = _stream(30, seed=5)
+    jobs = _jobs(24, seed=5, n_hi=1e6)
     srv = serve.Server(n_slots=4)
     done = srv.run(jobs)
     torch.cuda.synchronize()
-    assert len(done) == len(jobs)
-    assert max(s.job is None for s in srv.slots)
-    overlapped = sum(1 for a in done for b in done if a is not b and a.admitted < b.admitted < a.done)
-    print("requests overlapping on the device: %d" % overlapped, serve.summarize(done))
+    assert len(done) == len(jobs) and all(not j.error for j in done)
+    assert all(s.job is None for s in srv.slots)
+    ov = serve.device_overlap(done)
+    print("device concurrency %.2f, overlapping pairs %d, busy %.1f ms; max n %d"
+          % (ov["concurrency"], ov["overlapping_pairs"], ov["busy_ms"], max(j.n for j in done)))
+    assert ov["overlapping_pairs"] > 0
+    assert ov["concurrency"] > 1.1
     for j in done:
-        mix = j.u.cpu().numpy()
+        mix = j.u.numpy()
         alone = _solo(j)
         d = np.max(np.abs(mix - alone)) / np.max(np.abs(alone))
         assert d <= 1e-12, (j.rid, j.n, j.tol, d)
 
 
-def test_small_budget_forces_queueing_and_stays_correct():
-    """A budget that fits the largest request only: in-flight bytes never exceed it, the
-    largest request runs alone, smaller ones wait for memory, results stay correct."""
+def test_device_memory_stays_in_budget_and_requests_wait():
+    """A budget that fits the largest request only: the largest runs alone, smaller ones wait
+    for memory, the server allocates no device memory beyond its arena, results stay correct."""
     from paper_2606_19059_amd import serve
 
-    jobs = _stream(6, seed=9)
+    jobs = _jobs(6, seed=9)
+    probe = serve.Server(n_slots=1, hbm_budget=1 << 20)
     for j in jobs:
         j.precision = serve.precision_for(j.tol)
-    srv0 = serve.Server(n_slots=3)
-    sizes = [srv0.footprint(j) for j in jobs]
-    biggest = max(sizes)
+    biggest = max(probe.footprint(j) for j in jobs)
+    del probe
     srv = serve.Server(n_slots=3, hbm_budget=biggest + 1024)
+    for j in jobs:
+        srv.footprint(j)  # plans (library tables, outside torch) are made before measuring
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
+    reserved0 = torch.cuda.memory_reserved()
     done = srv.run(jobs)
-    assert len(done) == 6
+    torch.cuda.synchronize()
+    assert torch.cuda.max_memory_reserved() <= reserved0
+    assert srv.arena.size <= srv.budget
+    assert len(done) == 6 and all(not j.error for j in done)
     assert srv.max_in_flight_bytes <= srv.budget
     big = max(done, key=lambda j: j.footprint)
     for b in done:
         if b is not big:
-            assert not (big.admitted <= b.admitted < big.done or b.admitted <= big.admitted < b.done)
+            assert not (big.dev_start_ms < b.dev_end_ms and b.dev_start_ms < big.dev_end_ms)
     assert srv.memory_waits > 0
+    assert srv.arena.free_bytes() == srv.arena.size
     j = min(done, key=lambda j: j.n)
     ref = oracle.ewald_sum(j.x.numpy(), j.f.numpy(), j.box)
-    assert oracle.rel_err(j.u.cpu().numpy(), ref) <= j.tol
+    assert oracle.rel_err(j.u.numpy(), ref) <= j.tol
 
 
-def test_oversized_request_is_rejected():
+def test_small_requests_pass_a_waiting_large_one():
+    """Two large requests and four small ones, all waiting at t = 0, with room for one large
+    and the small ones: the small ones pass the second large request (which is served once
+    the first retires)."""
     from paper_2606_19059_amd import serve
 
-    jobs = _stream(2, seed=3)
+    big = _jobs(2, seed=21, n_lo=2e5, n_hi=2.5e5)
+    small = _jobs(4, seed=22, n_lo=1e3, n_hi=3e3)
+    jobs = big + small
+    for k, j in enumerate(jobs):
+        j.rid, j.arrival = k, 1e-6 * k
+        j.tol = 1e-6
+        j.precision = serve.precision_for(j.tol)
+    probe = serve.Server(n_slots=1, hbm_budget=1 << 20)
+    fb = max(probe.footprint(j) for j in big)
+    fs = sum(probe.footprint(j) for j in small)
+    del probe
+    srv = serve.Server(n_slots=4, hbm_budget=fb + fs + 4096)
+    done = srv.run(jobs)
+    assert all(not j.error for j in done)
+    assert srv.bypasses > 0
+    second = max(big, key=lambda j: j.admitted)
+    assert all(s.admitted < second.admitted for s in small)
+    for j in (big[0], small[0]):
+        d = np.max(np.abs(j.u.numpy() - _solo(j))) / np.max(np.abs(_solo(j)))
+        assert d <= 1e-12
+
+
+def test_refused_expired_and_cancelled_requests_never_run():
+    from paper_2606_19059_amd import serve
+
+    jobs = _jobs(6, seed=3, n_lo=2e4, n_hi=3e4)
+    good = jobs[0]
+    jobs[1].x = jobs[1].x.float()                         # wrong dtype
+    jobs[2].x = jobs[2].x.clone()
+    jobs[2].x[0, 3] = math.nan                            # non-finite position
+    jobs[3].box = (1.0, -1.0, 1.0)                        # bad box
+    jobs[4].cancel()                                      # cancelled while waiting
+    jobs[5].arrival, jobs[5].deadline = 0.0, 0.0           # must be admitted at once: behind
+    good.arrival = 0.0                                     # the first request on one slot
+    srv = serve.Server(n_slots=1, hbm_budget=256 << 20)
+    done = srv.run(jobs)
+    by = {j.rid: j for j in done}
+    assert not by[good.rid].error and by[good.rid].u is not None
+    assert "float64" in by[jobs[1].rid].error
+    assert "finite" in by[jobs[2].rid].error
+    assert "box" in by[jobs[3].rid].error
+    assert by[jobs[4].rid].error == "cancelled"
+    assert "deadline" in by[jobs[5].rid].error
+    assert srv.arena.free_bytes() == srv.arena.size
+
+
+def test_oversized_request_is_refused():
+    from paper_2606_19059_amd import serve
+
+    jobs = _jobs(2, seed=3)
     srv = serve.Server(n_slots=2, hbm_budget=1 << 20)
-    with pytest.raises(ValueError, match="budget"):
-        srv.run(jobs)
+    done = srv.run(jobs)
+    assert all("budget" in j.error for j in done)
+
+
+def test_failed_evaluation_fails_only_its_request():
+    """An evaluation that fails (forced from the host: the library's failure injection makes
+    the call return EWALD_EHIP before anything is enqueued) drops that request with its
+    message; the others are served and the arena is whole again."""
+    import paper_2606_19059_amd as E
+    from paper_2606_19059_amd import serve
+
+    jobs = _jobs(4, seed=31, n_lo=2e3, n_hi=5e3)
+    srv = serve.Server(n_slots=1, hbm_budget=512 << 20)
+    for j in jobs:
+        srv.footprint(j)
+    E.debug_fail_next(1)
+    done = srv.run(jobs)
+    failed = [j for j in done if j.error]
+    assert len(failed) == 1 and "injected" in failed[0].error
+    assert sum(1 for j in done if not j.error) == 3
+    assert srv.arena.free_bytes() == srv.arena.size
