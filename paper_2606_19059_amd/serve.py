@@ -171,6 +171,8 @@ class Server:
         """Cached plan per (box, tol, precision, size class): its grid, split and cutoff come
         from the plan cost model for that many particles.  Plans are never replaced while the
         server lives (in-flight work uses them)."""
+        if not job.precision:
+            job.precision = precision_for(job.tol)
         key = self._key(job)
         pl = self.plans.get(key)
         if pl is None:
