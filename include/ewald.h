@@ -165,6 +165,23 @@ int64_t ewald_workspace_bytes(ewald_plan_t plan, int64_t n);
 int ewald_eval(ewald_plan_t plan, int64_t n, const double* x, const double* f, double* u,
                void* workspace, int64_t workspace_bytes, void* stream);
 
+/* Bytes of the device array that serves as ewald_eval_noalloc's workspace (64 MiB). */
+#define EWALD_NOALLOC_MAX_WORKSPACE ((int64_t)64 << 20)
+
+/*
+ * ewald_eval for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same evaluation and kernels,
+ * with the workspace taken from an array of EWALD_NOALLOC_MAX_WORKSPACE bytes that the
+ * library holds on each device (set up when the first plan is created on that device, and
+ * kept until the process ends).  Allocates nothing.  The caller still passes x, f and u
+ * (device, (3, n) FP64).  Errors as ewald_eval, plus EWALD_ENOMEM (nothing enqueued) when
+ * ewald_workspace_bytes(plan, n) exceeds EWALD_NOALLOC_MAX_WORKSPACE, and EWALD_EINVAL
+ * when the current device is not the plan's.  Every call on one device uses the same
+ * array: calls that overlap on a device (other streams, other threads) race and give
+ * wrong results; serialise them.  Each call initialises what it reads of the array.
+ */
+int ewald_eval_noalloc(ewald_plan_t plan, int64_t n, const double* x, const double* f, double* u, void* stream);
+
 /*
  * Combined single and double layer sources (Sec. 2.3, "Combined single and double
  * layers"): every particle j carries a force f_j and two vectors q_j, n_j, and

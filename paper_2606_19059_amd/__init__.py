@@ -28,6 +28,8 @@ EWALD_FLAG_DETERMINISTIC = 1 << 11
 EWALD_FLAG_STRESSLET = 1 << 12
 EWALD_FLAG_CHECK_INPUTS = 1 << 13
 
+NOALLOC_MAX_WORKSPACE = 64 << 20  # EWALD_NOALLOC_MAX_WORKSPACE
+
 STAGES = ("sort", "p2p", "p2g", "fgc", "g2p", "total")
 
 # every function declared in include/ewald.h
@@ -38,6 +40,7 @@ EXPORTS = (
     "ewald_plan_destroy",
     "ewald_workspace_bytes",
     "ewald_eval",
+    "ewald_eval_noalloc",
     "ewald_eval_parts",
     "ewald_eval_combined",
     "ewald_eval_combined_parts",
@@ -114,6 +117,7 @@ def load(path: str | None = None):
     lib.ewald_workspace_bytes.restype = i64
     for name in ("ewald_eval", "ewald_eval_parts"):
         getattr(lib, name).argtypes = [vp, i64, vp, vp, vp] + ([vp] if name == "ewald_eval_parts" else []) + [vp, i64, vp]
+    lib.ewald_eval_noalloc.argtypes = [vp, i64, vp, vp, vp, vp]
     for name in ("ewald_eval_combined", "ewald_eval_combined_parts"):
         getattr(lib, name).argtypes = [vp, i64, vp, vp, vp, vp, vp] + (
             [vp] if name == "ewald_eval_combined_parts" else []) + [vp, i64, vp]
@@ -274,6 +278,16 @@ class Plan:
         u = out if out is not None else torch.empty_like(x)
         wp, wb = self._ws_args(n, workspace, x.device)
         _check(load().ewald_eval(self._h, n, _ptr(x), _ptr(f), _ptr(u), wp, wb, _stream_handle(stream)))
+        return u
+
+    def eval_noalloc(self, x, f, out=None, stream=None):
+        """eval without a caller workspace: the library's built-in scratch array serves
+        (at most NOALLOC_MAX_WORKSPACE bytes); calls overlapping on one device race."""
+        import torch
+
+        n = _check_particles(x, f)
+        u = out if out is not None else torch.empty_like(x)
+        _check(load().ewald_eval_noalloc(self._h, n, _ptr(x), _ptr(f), _ptr(u), _stream_handle(stream)))
         return u
 
     def eval_parts(self, x, f, workspace=None, stream=None):

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -317,6 +318,39 @@ int64_t layout_work(const Plan& pl, int64_t n, char* base, Work* w)
 }  // namespace ewald
 
 namespace {
+
+// Workspace of ewald_eval_noalloc: one array per device, in the library's code object, so
+// that evaluating needs no allocation.  In host code `scratch` names a host-side stand-in,
+// never the device memory: kernels and copies get the device address that
+// hipGetSymbolAddress returns for the current device (g_scratch, looked up once per device
+// by the first plan created on it).
+constexpr int64_t kScratchBytes = EWALD_NOALLOC_MAX_WORKSPACE;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (the current device), looked up on first use.
+int scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return fail(EWALD_EUNSUPPORTED, "device %d above %d", device, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch[device]) return EWALD_OK;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p || ((uintptr_t)p & 255) != 0) return fail(EWALD_EHIP, "scratch array address %p not 256-byte aligned", p);
+    g_scratch[device] = p;
+    return EWALD_OK;
+}
+
+void* scratch_ptr(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    return g_scratch[device];
+}
 
 int validate_and_resolve(const ewald_params* in, Plan* pl)
 {
@@ -707,6 +741,7 @@ int ewald_plan_create(const ewald_params* params, ewald_plan_t* plan_out)
         hipError_t e = hipGetDevice(&pl->device);
         if (e != hipSuccess) rc = hip_fail(e, "hipGetDevice");
     }
+    if (rc == EWALD_OK) rc = scratch_setup(pl->device);
     if (rc == EWALD_OK) rc = build_tables(pl);
     if (rc == EWALD_OK && pl->timers) {
         for (int k = 0; k <= kNumStages && rc == EWALD_OK; ++k) {
@@ -763,6 +798,25 @@ int ewald_eval(ewald_plan_t plan, int64_t n, const double* x, const double* f, d
                int64_t workspace_bytes, void* stream)
 {
     return run(plan, n, x, f, u, u, workspace, workspace_bytes, stream, Out::Full);
+}
+
+int ewald_eval_noalloc(ewald_plan_t plan, int64_t n, const double* x, const double* f, double* u, void* stream)
+{
+    if (!plan) return fail(EWALD_EINVAL, "null plan");
+    const Plan* pl = reinterpret_cast<const Plan*>(plan);
+    if (n < 0 || n > pl->p.n_max) return run(plan, n, x, f, u, u, nullptr, 0, stream, Out::Full);
+    const int64_t need = layout_work(*pl, n, nullptr, nullptr);
+    if (need > kScratchBytes)
+        return fail(EWALD_ENOMEM, "n = %lld needs a workspace of %lld bytes, above the %lld of the built-in scratch "
+                    "array (use ewald_eval with a caller workspace)", (long long)n, (long long)need,
+                    (long long)kScratchBytes);
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != pl->device) return fail(EWALD_EINVAL, "current device %d is not the plan's device %d", dev, pl->device);
+    void* ws = scratch_ptr(dev);
+    if (!ws) return fail(EWALD_EHIP, "scratch array of device %d not set up", dev);
+    return run(plan, n, x, f, u, u, ws, kScratchBytes, stream, Out::Full);
 }
 
 int ewald_eval_parts(ewald_plan_t plan, int64_t n, const double* x, const double* f, double* u_near,
