@@ -259,6 +259,8 @@ def main():
                     help="skip the cost-model plan and Kaiser-Bessel legs")
     ap.add_argument("--serve-requests", type=int, default=200,
                     help="requests in the serving leg (Poisson stream of independent suspensions; 0: skip)")
+    ap.add_argument("--entry", default="eval", choices=("eval", "overlap"),
+                    help="entry point timed: ewald_eval, or ewald_eval_overlap (P2P on a second stream)")
     ap.add_argument("--configs", default="c1,c3,c4",
                     help="other benchmark configurations timed beside the main one (comma list; '' for none)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -298,9 +300,16 @@ def main():
                                                    "stencil", "workspace_bytes")}))
     ws = plan.workspace(wl.n, dev)
     u = torch.empty_like(x)
+    side = torch.cuda.Stream(device=dev)  # the near field's stream for the overlapped entry point
+
+    def step(entry):
+        if entry == "overlap":
+            plan.eval_overlap(x, f, out=u, workspace=ws, near_stream=side)
+        else:
+            plan.eval(x, f, out=u, workspace=ws)
 
     for _ in range(args.warmup):
-        plan.eval(x, f, out=u, workspace=ws)
+        step(args.entry)
     torch.cuda.synchronize()
     log("warmup done")
 
@@ -310,7 +319,7 @@ def main():
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ts = time.perf_counter()
-        plan.eval(x, f, out=u, workspace=ws)
+        step(args.entry)
         torch.cuda.synchronize()
         step_ms.append((time.perf_counter() - ts) * 1e3)
         st = plan.stage_ms()
@@ -321,6 +330,19 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     stages = {k: v / args.steps for k, v in stage_sum.items()}
     log("stages (ms):", json.dumps({k: round(v, 4) for k, v in stages.items()}))
+    # the other entry point on the same inputs (same results; P2P on one or two streams)
+    other = "eval" if args.entry == "overlap" else "overlap"
+    for _ in range(2):
+        step(other)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        step(other)
+    torch.cuda.synchronize()
+    other_ms = (time.perf_counter() - t1) * 1e3 / args.steps
+    log("%s entry point: %.3f ms per step" % (other, other_ms))
+    step(args.entry)
+    torch.cuda.synchronize()
 
     # accuracy on sampled targets against the classical FP64 oracle (also the CPU baseline)
     rel_err = None
@@ -478,6 +500,8 @@ def main():
             "n": wl.n, "tol": wl.tol, "grid": list(info["grid"]), "P": info["P"], "xi": info["xi"],
             "r_c": info["r_c"], "rel_err_sampled": rel_err, "stage_ms": stages,
             "p2g_GBs": p2g_gbs, "p50_ms": p50, "p99_ms": p99, "stage_roofline": per_stage,
+            "entry_point": "ewald_eval_overlap" if args.entry == "overlap" else "ewald_eval",
+            "other_entry_point_ms_per_step": {("ewald_eval_overlap" if other == "overlap" else "ewald_eval"): other_ms},
         },
         "serving": serving,
         "configs": configs,

@@ -204,6 +204,22 @@ int ewald_eval_combined_parts(ewald_plan_t plan, int64_t n, const double* x, con
                               int64_t workspace_bytes, void* stream);
 
 /*
+ * ewald_eval with the near field (P2P) on a second stream: P2P does not depend on P2G or the
+ * FFTs (Sec. 6.5 notes that they can overlap), so after the sort `stream` records
+ * `fork_event`, `near_stream` waits for it and runs P2P, then records `join_event`, for which
+ * `stream` waits before G2P; P2G, FFT, CNV and IFFT run on `stream` meanwhile.  When the call
+ * returns, all work is ordered before later work on `stream` (near_stream carries nothing
+ * after join_event).  The caller owns both streams and both events (hipEvent_t, e.g. created
+ * with hipEventDisableTiming); concurrent evaluations need their own streams, events and
+ * workspaces.  Same results and arguments as ewald_eval; EWALD_EINVAL for null or equal
+ * streams or null events with n > 0.  With EWALD_FLAG_STAGE_TIMERS, ewald_stage_ms reports
+ * P2P and P2G each from the fork and G2P from the later of the join and the far field.
+ */
+int ewald_eval_overlap(ewald_plan_t plan, int64_t n, const double* x, const double* f, double* u,
+                       void* workspace, int64_t workspace_bytes, void* stream, void* near_stream,
+                       void* fork_event, void* join_event);
+
+/*
  * Diagnostic split of ewald_eval: u_near = the P2P sum (Sec. 2.1,
  * eq. (potentials-near)) and u_far = the interpolated far field u^F_h
  * (eq. (g2p)), both (3, n) FP64 device arrays in the caller's particle order,

@@ -41,6 +41,7 @@ EXPORTS = (
     "ewald_workspace_bytes",
     "ewald_eval",
     "ewald_eval_noalloc",
+    "ewald_eval_overlap",
     "ewald_eval_parts",
     "ewald_eval_combined",
     "ewald_eval_combined_parts",
@@ -118,6 +119,7 @@ def load(path: str | None = None):
     for name in ("ewald_eval", "ewald_eval_parts"):
         getattr(lib, name).argtypes = [vp, i64, vp, vp, vp] + ([vp] if name == "ewald_eval_parts" else []) + [vp, i64, vp]
     lib.ewald_eval_noalloc.argtypes = [vp, i64, vp, vp, vp, vp]
+    lib.ewald_eval_overlap.argtypes = [vp, i64, vp, vp, vp, vp, i64, vp, vp, vp, vp]
     for name in ("ewald_eval_combined", "ewald_eval_combined_parts"):
         getattr(lib, name).argtypes = [vp, i64, vp, vp, vp, vp, vp] + (
             [vp] if name == "ewald_eval_combined_parts" else []) + [vp, i64, vp]
@@ -289,6 +291,40 @@ class Plan:
         u = out if out is not None else torch.empty_like(x)
         _check(load().ewald_eval_noalloc(self._h, n, _ptr(x), _ptr(f), _ptr(u), _stream_handle(stream)))
         return u
+
+    def eval_overlap(self, x, f, out=None, workspace=None, stream=None, near_stream=None):
+        """eval with P2P on a second stream beside P2G and the FFTs (joined before G2P).
+        The plan keeps one second stream and a pair of events for calls without
+        `near_stream`; concurrent calls on other streams pass their own."""
+        import torch
+
+        n = _check_particles(x, f)
+        u = out if out is not None else torch.empty_like(x)
+        wp, wb = self._ws_args(n, workspace, x.device)
+        s = stream if stream is not None else torch.cuda.current_stream(x.device)
+        if near_stream is None:
+            if getattr(self, "_near", None) is None:
+                self._near = torch.cuda.Stream(device=x.device)  # default priority
+            near_stream = self._near
+        evs = self._overlap_events(near_stream)
+        _check(load().ewald_eval_overlap(self._h, n, _ptr(x), _ptr(f), _ptr(u), wp, wb, _stream_handle(s),
+                                         _stream_handle(near_stream), ctypes.c_void_p(evs[0].cuda_event),
+                                         ctypes.c_void_p(evs[1].cuda_event)))
+        return u
+
+    def _overlap_events(self, near_stream):
+        """Fork and join events for overlapped calls using `near_stream` (created once and
+        recorded once so that the HIP events exist)."""
+        import torch
+
+        cache = self.__dict__.setdefault("_ov_events", {})
+        key = near_stream.cuda_stream
+        if key not in cache:
+            evs = (torch.cuda.Event(), torch.cuda.Event())
+            for e in evs:
+                e.record(near_stream)
+            cache[key] = evs
+        return cache[key]
 
     def eval_parts(self, x, f, workspace=None, stream=None):
         """(u_near, u_far): the P2P sum and the interpolated far field, caller order."""

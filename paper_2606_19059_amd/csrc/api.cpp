@@ -646,9 +646,11 @@ int check_eval_args(ewald_plan_t plan, int64_t n, const void* x, const void* f, 
 
 enum class Out { Full, Parts, Spread, FarGrid, CountPairs };
 
+// near != nullptr: P2P runs on the stream `near`, forked from `stream` after the sort through the
+// event `fork` and joined back through `join` before G2P (P2P is independent of P2G and the FFTs)
 int run(ewald_plan_t plan, int64_t n64, const double* x, const double* f, void* o1, void* o2, void* ws,
         int64_t wsb, void* stream, Out what, bool st = false, const double* q = nullptr, const double* nrm = nullptr,
-        int64_t out_bytes = 0)
+        int64_t out_bytes = 0, hipStream_t near = nullptr, hipEvent_t fork = nullptr, hipEvent_t join = nullptr)
 {
     Work w;
     if ((what == Out::Spread || what == Out::FarGrid) && plan) {
@@ -698,10 +700,19 @@ int run(ewald_plan_t plan, int64_t n64, const double* x, const double* f, void* 
     }
     if (st && (e = launch_gather_st(*pl, w, n, q, nrm, s)) != hipSuccess) return hip_fail(e, "stresslet gather");
     mark(1);
-    if (what == Out::Full || what == Out::Parts) {
-        if ((e = launch_p2p(*pl, w, n, s, st)) != hipSuccess) return hip_fail(e, "P2P");
+    if (near) {
+        // the near field on its own stream, beside P2G and the FFTs
+        if ((e = hipEventRecord(fork, s)) != hipSuccess) return hip_fail(e, "fork event");
+        if ((e = hipStreamWaitEvent(near, fork, 0)) != hipSuccess) return hip_fail(e, "fork wait");
+        if ((e = launch_p2p(*pl, w, n, near, st)) != hipSuccess) return hip_fail(e, "P2P");
+        if (t) (void)hipEventRecord(pl->ev[2], near);
+        if ((e = hipEventRecord(join, near)) != hipSuccess) return hip_fail(e, "join event");
+    } else {
+        if (what == Out::Full || what == Out::Parts) {
+            if ((e = launch_p2p(*pl, w, n, s, st)) != hipSuccess) return hip_fail(e, "P2P");
+        }
+        mark(2);
     }
-    mark(2);
     if ((e = launch_p2g(*pl, w, n, s, st)) != hipSuccess) return hip_fail(e, "P2G");
     mark(3);
     const size_t gbytes = (size_t)pl->info.grid_bytes;
@@ -715,13 +726,17 @@ int run(ewald_plan_t plan, int64_t n64, const double* x, const double* f, void* 
         e = hipMemcpyAsync(o1, w.grid, gbytes, hipMemcpyDeviceToDevice, s);
         return e == hipSuccess ? EWALD_OK : hip_fail(e, "grid copy");
     }
+    if (near && (e = hipStreamWaitEvent(s, join, 0)) != hipSuccess) return hip_fail(e, "join wait");
     if (what == Out::Full)
         e = launch_g2p(*pl, w, n, f, (double*)o1, nullptr, nullptr, s);
     else
         e = launch_g2p(*pl, w, n, f, nullptr, (double*)o1, (double*)o2, s);
     if (e != hipSuccess) return hip_fail(e, "G2P");
     mark(5);
-    if (t) pl->ev_valid = true;
+    if (t) {
+        pl->ev_valid = true;
+        pl->ev_overlapped = near != nullptr;
+    }
     return EWALD_OK;
 }
 
@@ -819,6 +834,16 @@ int ewald_eval_noalloc(ewald_plan_t plan, int64_t n, const double* x, const doub
     return run(plan, n, x, f, u, u, ws, kScratchBytes, stream, Out::Full);
 }
 
+int ewald_eval_overlap(ewald_plan_t plan, int64_t n, const double* x, const double* f, double* u, void* workspace,
+                       int64_t workspace_bytes, void* stream, void* near_stream, void* fork_event, void* join_event)
+{
+    if (n > 0 && (!near_stream || !fork_event || !join_event))
+        return fail(EWALD_EINVAL, "null near-field stream or event");
+    if (n > 0 && near_stream == stream) return fail(EWALD_EINVAL, "the near-field stream must differ from the stream");
+    return run(plan, n, x, f, u, u, workspace, workspace_bytes, stream, Out::Full, false, nullptr, nullptr, 0,
+               (hipStream_t)near_stream, (hipEvent_t)fork_event, (hipEvent_t)join_event);
+}
+
 int ewald_eval_parts(ewald_plan_t plan, int64_t n, const double* x, const double* f, double* u_near,
                      double* u_far, void* workspace, int64_t workspace_bytes, void* stream)
 {
@@ -871,12 +896,28 @@ int ewald_stage_ms(ewald_plan_t plan, float* ms, int32_t count)
     if (!pl->timers) return fail(EWALD_EINVAL, "plan was created without EWALD_FLAG_STAGE_TIMERS");
     if (!pl->ev_valid) return fail(EWALD_EINVAL, "no timed evaluation recorded yet");
     float v[kNumStages];
-    for (int k = 0; k < kNumStages - 1; ++k) {
-        hipError_t e = hipEventElapsedTime(&v[k], pl->ev[k], pl->ev[k + 1]);
+    if (pl->ev_overlapped) {
+        // P2P ran beside P2G and the FFTs: each stage from its own start (the fork for P2P and
+        // P2G), G2P from the later of the far field and the join
+        float tk[kNumStages];
+        for (int k = 1; k < kNumStages; ++k) {
+            hipError_t e = hipEventElapsedTime(&tk[k], pl->ev[0], pl->ev[k]);
+            if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        }
+        v[0] = tk[1];
+        v[1] = tk[2] - tk[1];
+        v[2] = tk[3] - tk[1];
+        v[3] = tk[4] - tk[3];
+        v[4] = tk[5] - std::max(tk[4], tk[2]);
+        v[5] = tk[5];
+    } else {
+        for (int k = 0; k < kNumStages - 1; ++k) {
+            hipError_t e = hipEventElapsedTime(&v[k], pl->ev[k], pl->ev[k + 1]);
+            if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        }
+        hipError_t e = hipEventElapsedTime(&v[kNumStages - 1], pl->ev[0], pl->ev[kNumStages - 1]);
         if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
     }
-    hipError_t e = hipEventElapsedTime(&v[kNumStages - 1], pl->ev[0], pl->ev[kNumStages - 1]);
-    if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
     const int k = std::min<int>(count, kNumStages);
     for (int i = 0; i < k; ++i) ms[i] = v[i];
     return k;

@@ -91,6 +91,7 @@ struct Plan {
     hipEvent_t ev[kNumStages + 1];
     float stage_ms[kNumStages];
     bool ev_valid;
+    bool ev_overlapped;    // the timed evaluation ran P2P on a second stream
 };
 
 // Device pointers carved out of the caller's workspace.

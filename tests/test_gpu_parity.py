@@ -410,3 +410,53 @@ def test_input_check_mode_refuses_non_finite_inputs():
             pl.eval(dev(xx), dev(ff), out=u)
         assert ei.value.code == E.EWALD_EINVAL and "non-finite" in str(ei.value)
         assert np.all(host(u) == 3.0)
+
+
+# ---------------------------------------------------------------- near field on a second stream
+
+
+@pytest.mark.parametrize("name,n,precision", [("cube32_P8", 2000, "fp64"), ("aniso_P12", 1531, "fp32"),
+                                              ("zlong_P8", 3000, "fp64")])
+def test_overlap_matches_eval(name, n, precision):
+    """ewald_eval_overlap (P2P on a second stream) gives ewald_eval's result to rounding (both
+    add the pair terms with atomics), call after call, with the plan's timers consistent."""
+    E = _E()
+    box, grid, xi, rc, P, m = CASES[name]
+    tol = 1e-11 if precision == "fp64" else 1e-5
+    pl = E.Plan(box, tol, xi=xi, r_c=rc, grid=grid, P=P, window_shape=m, n_max=n, precision=precision, timers=True)
+    x, f = W.particles(n, box, seed=51)
+    X, F = dev(x), dev(f)
+    ref = host(pl.eval(X, F))
+    side = torch.cuda.Stream()
+    for _ in range(3):
+        u = host(pl.eval_overlap(X, F, near_stream=side))
+        assert np.max(np.abs(u - ref)) <= 1e-12 * np.max(np.abs(ref))
+    st = pl.stage_ms()
+    assert st["total"] > 0 and st["p2p"] > 0 and st["p2g"] > 0
+    assert st["p2p"] <= st["total"] and st["g2p"] <= st["total"]
+    # the oracle agrees with the overlapped result too
+    if name == "cube32_P8":
+        un_ref = oracle.real_space(x, f, box, xi, rc)
+        uf_ref = S.far_field(x, f, box, grid, xi, P, m)
+        want = un_ref + uf_ref + oracle.self_term(f, xi)
+        assert maxrel(u, want) < 1e-10
+
+
+def test_overlap_rejects_missing_or_equal_streams():
+    import ctypes
+
+    E = _E()
+    pl = make_plan(E, "cube32_P8", 100)
+    x, f = W.particles(100, (1, 1, 1), seed=1)
+    X, F = dev(x), dev(f)
+    u = torch.empty_like(X)
+    ws = pl.workspace(100)
+    s = torch.cuda.current_stream()
+    lib = E.load()
+    args = (pl.handle, 100, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(F.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+            ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(s.cuda_stream))
+    ev = torch.cuda.Event()
+    ev.record(s)
+    assert lib.ewald_eval_overlap(*args, None, ctypes.c_void_p(ev.cuda_event), ctypes.c_void_p(ev.cuda_event)) == E.EWALD_EINVAL
+    assert lib.ewald_eval_overlap(*args, ctypes.c_void_p(s.cuda_stream), ctypes.c_void_p(ev.cuda_event),
+                                  ctypes.c_void_p(ev.cuda_event)) == E.EWALD_EINVAL
