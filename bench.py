@@ -261,6 +261,8 @@ def main():
                     help="requests in the serving leg (Poisson stream of independent suspensions; 0: skip)")
     ap.add_argument("--entry", default="eval", choices=("eval", "overlap"),
                     help="entry point timed: ewald_eval, or ewald_eval_overlap (P2P on a second stream)")
+    ap.add_argument("--compare-entries", action="store_true",
+                    help="also time the other entry point (eval / overlap) on the same inputs")
     ap.add_argument("--configs", default="c1,c3,c4",
                     help="other benchmark configurations timed beside the main one (comma list; '' for none)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -332,17 +334,19 @@ def main():
     log("stages (ms):", json.dumps({k: round(v, 4) for k, v in stages.items()}))
     # the other entry point on the same inputs (same results; P2P on one or two streams)
     other = "eval" if args.entry == "overlap" else "overlap"
-    for _ in range(2):
-        step(other)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
-        step(other)
-    torch.cuda.synchronize()
-    other_ms = (time.perf_counter() - t1) * 1e3 / args.steps
-    log("%s entry point: %.3f ms per step" % (other, other_ms))
-    step(args.entry)
-    torch.cuda.synchronize()
+    other_ms = None
+    if args.compare_entries:
+        for _ in range(2):
+            step(other)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            step(other)
+        torch.cuda.synchronize()
+        other_ms = (time.perf_counter() - t1) * 1e3 / args.steps
+        log("%s entry point: %.3f ms per step" % (other, other_ms))
+        step(args.entry)
+        torch.cuda.synchronize()
 
     # accuracy on sampled targets against the classical FP64 oracle (also the CPU baseline)
     rel_err = None
@@ -501,7 +505,8 @@ def main():
             "r_c": info["r_c"], "rel_err_sampled": rel_err, "stage_ms": stages,
             "p2g_GBs": p2g_gbs, "p50_ms": p50, "p99_ms": p99, "stage_roofline": per_stage,
             "entry_point": "ewald_eval_overlap" if args.entry == "overlap" else "ewald_eval",
-            "other_entry_point_ms_per_step": {("ewald_eval_overlap" if other == "overlap" else "ewald_eval"): other_ms},
+            "other_entry_point_ms_per_step": ({("ewald_eval_overlap" if other == "overlap" else "ewald_eval"): other_ms}
+                                              if other_ms is not None else None),
         },
         "serving": serving,
         "configs": configs,
