@@ -219,6 +219,27 @@ int ewald_eval_overlap(ewald_plan_t plan, int64_t n, const double* x, const doub
                        void* workspace, int64_t workspace_bytes, void* stream, void* near_stream,
                        void* fork_event, void* join_event);
 
+/* Most systems one ewald_eval_batch call evaluates. */
+#define EWALD_MAX_BATCH 64
+
+/*
+ * Batched evaluation of `count` independent systems that share the plan (box, tolerance,
+ * parameters): system r is the particles [offsets[r], offsets[r+1]) of x, f and u, each
+ * (3, offsets[count]) FP64 device arrays, and is summed over its own periodic images only
+ * (Algorithm "se" per system).  One launch sequence serves all systems, so small systems
+ * cost little more than one (the serving loop groups small requests this way).  `offsets`
+ * is a host array of count + 1 non-decreasing entries, offsets[0] = 0, each system at most
+ * the plan's n_max particles (offsets[count] may exceed it).  The workspace must hold
+ * ewald_workspace_bytes_batch(plan, count, offsets) bytes.  Errors as ewald_eval, plus
+ * EWALD_EINVAL for count outside [1, EWALD_MAX_BATCH] or bad offsets, and
+ * EWALD_EUNSUPPORTED for stresslet plans.
+ */
+int ewald_eval_batch(ewald_plan_t plan, int32_t count, const int64_t* offsets, const double* x, const double* f,
+                     double* u, void* workspace, int64_t workspace_bytes, void* stream);
+
+/* Workspace bytes of ewald_eval_batch for these systems (negative status on error). */
+int64_t ewald_workspace_bytes_batch(ewald_plan_t plan, int32_t count, const int64_t* offsets);
+
 /*
  * Diagnostic split of ewald_eval: u_near = the P2P sum (Sec. 2.1,
  * eq. (potentials-near)) and u_far = the interpolated far field u^F_h

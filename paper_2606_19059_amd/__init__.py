@@ -29,6 +29,7 @@ EWALD_FLAG_STRESSLET = 1 << 12
 EWALD_FLAG_CHECK_INPUTS = 1 << 13
 
 NOALLOC_MAX_WORKSPACE = 64 << 20  # EWALD_NOALLOC_MAX_WORKSPACE
+MAX_BATCH = 64  # EWALD_MAX_BATCH
 
 STAGES = ("sort", "p2p", "p2g", "fgc", "g2p", "total")
 
@@ -40,6 +41,8 @@ EXPORTS = (
     "ewald_plan_destroy",
     "ewald_workspace_bytes",
     "ewald_eval",
+    "ewald_eval_batch",
+    "ewald_workspace_bytes_batch",
     "ewald_eval_noalloc",
     "ewald_eval_overlap",
     "ewald_eval_parts",
@@ -119,6 +122,9 @@ def load(path: str | None = None):
     for name in ("ewald_eval", "ewald_eval_parts"):
         getattr(lib, name).argtypes = [vp, i64, vp, vp, vp] + ([vp] if name == "ewald_eval_parts" else []) + [vp, i64, vp]
     lib.ewald_eval_noalloc.argtypes = [vp, i64, vp, vp, vp, vp]
+    lib.ewald_eval_batch.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64), vp, vp, vp, vp, i64, vp]
+    lib.ewald_workspace_bytes_batch.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64)]
+    lib.ewald_workspace_bytes_batch.restype = i64
     lib.ewald_eval_overlap.argtypes = [vp, i64, vp, vp, vp, vp, i64, vp, vp, vp, vp]
     for name in ("ewald_eval_combined", "ewald_eval_combined_parts"):
         getattr(lib, name).argtypes = [vp, i64, vp, vp, vp, vp, vp] + (
@@ -280,6 +286,35 @@ class Plan:
         u = out if out is not None else torch.empty_like(x)
         wp, wb = self._ws_args(n, workspace, x.device)
         _check(load().ewald_eval(self._h, n, _ptr(x), _ptr(f), _ptr(u), wp, wb, _stream_handle(stream)))
+        return u
+
+    @staticmethod
+    def _offsets(sizes):
+        off = (ctypes.c_int64 * (len(sizes) + 1))()
+        for k, m in enumerate(sizes):
+            off[k + 1] = off[k] + int(m)
+        return off
+
+    def workspace_bytes_batch(self, sizes):
+        return _check(load().ewald_workspace_bytes_batch(self._h, len(sizes), self._offsets(sizes)))
+
+    def eval_batch(self, x, f, sizes, out=None, workspace=None, stream=None):
+        """u for independent systems sharing this plan: system k is the next sizes[k]
+        columns of x and f ((3, sum(sizes)) device arrays), summed over its own images."""
+        import torch
+
+        n = _check_particles(x, f)
+        if sum(int(m) for m in sizes) != n:
+            raise ValueError("sizes must add up to the number of particles")
+        u = out if out is not None else torch.empty_like(x)
+        off = self._offsets(sizes)
+        need = self.workspace_bytes_batch(sizes)
+        if workspace is None:
+            if self._ws is None or self._ws.numel() < need:
+                self._ws = torch.empty(max(need, 256), dtype=torch.uint8, device=x.device)
+            workspace = self._ws
+        _check(load().ewald_eval_batch(self._h, len(sizes), off, _ptr(x), _ptr(f), _ptr(u), _ptr(workspace),
+                                       ctypes.c_int64(workspace.numel()), _stream_handle(stream)))
         return u
 
     def eval_noalloc(self, x, f, out=None, stream=None):

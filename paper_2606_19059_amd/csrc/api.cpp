@@ -284,9 +284,10 @@ int64_t align256(int64_t v) { return (v + 255) & ~(int64_t)255; }
 
 namespace ewald {
 
-int64_t layout_work(const Plan& pl, int64_t n, char* base, Work* w)
+int64_t layout_work(const Plan& pl, int64_t n, char* base, Work* w, int nsys)
 {
     const Geometry& g = pl.g;
+    const int64_t ncells = (int64_t)g.ncells * nsys, ntiles = (int64_t)g.ntiles * nsys;  // all systems
     int64_t off = 0;
     auto take = [&](int64_t bytes) -> char* {
         char* p = base ? base + off : nullptr;
@@ -300,16 +301,16 @@ int64_t layout_work(const Plan& pl, int64_t n, char* base, Work* w)
     Work* o = w ? w : &tmp;
     o->key = (int*)take(4 * nn);
     o->perm = (int*)take(4 * nn);
-    o->count = (int*)take(4 * (int64_t)g.ncells);
-    o->start = (int*)take(4 * ((int64_t)g.ncells + 1));
-    o->chunk_off = (int*)take(4 * ((int64_t)g.ntiles + 1));
-    o->part = (int*)take(4 * (int64_t)scan_part_elems(std::max(g.ncells, g.ntiles)));
+    o->count = (int*)take(4 * ncells);
+    o->start = (int*)take(4 * (ncells + 1));
+    o->chunk_off = (int*)take(4 * (ntiles + 1));
+    o->part = (int*)take(4 * (int64_t)scan_part_elems((int)std::max(ncells, ntiles)));
     o->cell_lists = (int*)take(4 * cell_list_elems(nn));
     o->rec = (void*)take((int64_t)recsz * nn);
     o->u_near = (double*)take(8 * 3 * nn);
     o->srec = pl.stresslet ? (double*)take(8 * 6 * nn) : nullptr;
-    o->grid = (void*)take((int64_t)real * (pl.stresslet ? 9 : 3) * g.ncells);
-    const int64_t nh = p2g_halo_elems(pl);
+    o->grid = (void*)take((int64_t)real * (pl.stresslet ? 9 : 3) * ncells);
+    const int64_t nh = p2g_halo_elems(pl) * nsys;
     o->p2g_halo = nh > 0 ? (double*)take(8 * nh) : nullptr;
     o->bytes = off;
     return off;
@@ -483,6 +484,7 @@ int validate_and_resolve(const ewald_params* in, Plan* pl)
     g.B = B;
     g.log2B = ilog2(B);
     g.ncells = g.M[0] * g.M[1] * g.M[2];
+    g.nsys = 1;
     g.ntiles = 1;
     for (int d = 0; d < 3; ++d) {
         g.NT[d] = g.M[d] / B;
@@ -629,18 +631,44 @@ int build_tables(Plan* pl)
 }
 
 int check_eval_args(ewald_plan_t plan, int64_t n, const void* x, const void* f, const void* o1,
-                    const void* o2, void* ws, int64_t wsb, Work* w)
+                    const void* o2, void* ws, int64_t wsb, Work* w, int nsys = 1)
 {
     if (!plan) return fail(EWALD_EINVAL, "null plan");
     const Plan* pl = reinterpret_cast<const Plan*>(plan);
     if (n < 0) return fail(EWALD_EINVAL, "n = %lld < 0", (long long)n);
-    if (n > pl->p.n_max) return fail(EWALD_EINVAL, "n = %lld exceeds the plan's n_max = %lld", (long long)n, (long long)pl->p.n_max);
+    if (nsys == 1 && n > pl->p.n_max)
+        return fail(EWALD_EINVAL, "n = %lld exceeds the plan's n_max = %lld", (long long)n, (long long)pl->p.n_max);
     if (n == 0) return EWALD_OK;
     if (!x || !f || !o1 || !o2) return fail(EWALD_EINVAL, "null array pointer");
     if (!ws) return fail(EWALD_EINVAL, "null workspace");
     if (((uintptr_t)ws & 255) != 0) return fail(EWALD_EINVAL, "workspace not 256-byte aligned");
-    const int64_t need = layout_work(*pl, n, (char*)ws, w);
+    const int64_t need = layout_work(*pl, n, (char*)ws, w, nsys);
     if (wsb < need) return fail(EWALD_ENOMEM, "workspace of %lld bytes below the %lld needed", (long long)wsb, (long long)need);
+    return EWALD_OK;
+}
+
+// Validate a batch description (host offsets, count + 1 entries) and fill *b.
+int make_batch(const Plan* pl, int32_t count, const int64_t* offsets, Batch* b)
+{
+    if (count < 1 || count > kMaxBatch) return fail(EWALD_EINVAL, "count = %d outside [1, %d]", count, kMaxBatch);
+    if (!offsets) return fail(EWALD_EINVAL, "null offsets");
+    if (offsets[0] != 0) return fail(EWALD_EINVAL, "offsets[0] = %lld must be 0", (long long)offsets[0]);
+    if (pl->stresslet) return fail(EWALD_EUNSUPPORTED, "batches of stresslet plans are not supported");
+    if ((int64_t)pl->g.ncells * count + 1 > INT32_MAX)
+        return fail(EWALD_EUNSUPPORTED, "%d systems of %d grid cells exceed the cell list's 32-bit range", count,
+                    pl->g.ncells);
+    b->count = count;
+    for (int r = 0; r < count; ++r) {
+        const int64_t nr = offsets[r + 1] - offsets[r];
+        if (nr < 0) return fail(EWALD_EINVAL, "offsets decrease at %d", r);
+        if (nr > pl->p.n_max)
+            return fail(EWALD_EINVAL, "system %d has %lld particles, above the plan's n_max = %lld", r, (long long)nr,
+                        (long long)pl->p.n_max);
+        b->off[r] = (int)offsets[r];
+    }
+    if (offsets[count] > ((int64_t)1 << 30)) return fail(EWALD_EUNSUPPORTED, "batch of more than 2^30 particles");
+    b->off[count] = (int)offsets[count];
+    for (int r = count + 1; r <= kMaxBatch; ++r) b->off[r] = b->off[count];
     return EWALD_OK;
 }
 
@@ -648,11 +676,20 @@ enum class Out { Full, Parts, Spread, FarGrid, CountPairs };
 
 // near != nullptr: P2P runs on the stream `near`, forked from `stream` after the sort through the
 // event `fork` and joined back through `join` before G2P (P2P is independent of P2G and the FFTs)
+// batch != nullptr: the n64 particles are batch->count independent systems of the plan
 int run(ewald_plan_t plan, int64_t n64, const double* x, const double* f, void* o1, void* o2, void* ws,
         int64_t wsb, void* stream, Out what, bool st = false, const double* q = nullptr, const double* nrm = nullptr,
-        int64_t out_bytes = 0, hipStream_t near = nullptr, hipEvent_t fork = nullptr, hipEvent_t join = nullptr)
+        int64_t out_bytes = 0, hipStream_t near = nullptr, hipEvent_t fork = nullptr, hipEvent_t join = nullptr,
+        const Batch* batch = nullptr)
 {
     Work w;
+    Batch one;
+    if (!batch) {
+        one.count = 1;
+        for (int r = 0; r <= kMaxBatch; ++r) one.off[r] = (r == 0) ? 0 : (int)std::min<int64_t>(n64, INT32_MAX);
+        batch = &one;
+    }
+    const int nsys = batch->count;
     if ((what == Out::Spread || what == Out::FarGrid) && plan) {
         const int64_t need = reinterpret_cast<const Plan*>(plan)->info.grid_bytes;
         if (n64 > 0 && out_bytes < need)
@@ -665,7 +702,7 @@ int run(ewald_plan_t plan, int64_t n64, const double* x, const double* f, void* 
             return fail(EWALD_EINVAL, "stresslet sources need a plan created with EWALD_FLAG_STRESSLET");
         if (n64 > 0 && (!q || !nrm)) return fail(EWALD_EINVAL, "null stresslet vector pointer");
     }
-    int rc = check_eval_args(plan, n64, x, f, o1, what == Out::Parts ? o2 : o1, ws, wsb, &w);
+    int rc = check_eval_args(plan, n64, x, f, o1, what == Out::Parts ? o2 : o1, ws, wsb, &w, nsys);
     if (rc != EWALD_OK || n64 == 0) return rc;
     if (g_fail_next > 0) {
         --g_fail_next;
@@ -693,9 +730,9 @@ int run(ewald_plan_t plan, int64_t n64, const double* x, const double* f, void* 
         if (t) (void)hipEventRecord(pl->ev[k], s);
     };
     mark(0);
-    if ((e = launch_sort(*pl, w, n, x, f, s)) != hipSuccess) return hip_fail(e, "sort");
+    if ((e = launch_sort(*pl, w, n, x, f, *batch, s)) != hipSuccess) return hip_fail(e, "sort");
     if (what == Out::CountPairs) {
-        e = launch_count_pairs(*pl, w, n, (unsigned long long*)o1, s);
+        e = launch_count_pairs(*pl, w, n, (unsigned long long*)o1, s, nsys);
         return e == hipSuccess ? EWALD_OK : hip_fail(e, "pair count");
     }
     if (st && (e = launch_gather_st(*pl, w, n, q, nrm, s)) != hipSuccess) return hip_fail(e, "stresslet gather");
@@ -704,23 +741,23 @@ int run(ewald_plan_t plan, int64_t n64, const double* x, const double* f, void* 
         // the near field on its own stream, beside P2G and the FFTs
         if ((e = hipEventRecord(fork, s)) != hipSuccess) return hip_fail(e, "fork event");
         if ((e = hipStreamWaitEvent(near, fork, 0)) != hipSuccess) return hip_fail(e, "fork wait");
-        if ((e = launch_p2p(*pl, w, n, near, st)) != hipSuccess) return hip_fail(e, "P2P");
+        if ((e = launch_p2p(*pl, w, n, near, st, nsys)) != hipSuccess) return hip_fail(e, "P2P");
         if (t) (void)hipEventRecord(pl->ev[2], near);
         if ((e = hipEventRecord(join, near)) != hipSuccess) return hip_fail(e, "join event");
     } else {
         if (what == Out::Full || what == Out::Parts) {
-            if ((e = launch_p2p(*pl, w, n, s, st)) != hipSuccess) return hip_fail(e, "P2P");
+            if ((e = launch_p2p(*pl, w, n, s, st, nsys)) != hipSuccess) return hip_fail(e, "P2P");
         }
         mark(2);
     }
-    if ((e = launch_p2g(*pl, w, n, s, st)) != hipSuccess) return hip_fail(e, "P2G");
+    if ((e = launch_p2g(*pl, w, n, s, st, nsys)) != hipSuccess) return hip_fail(e, "P2G");
     mark(3);
     const size_t gbytes = (size_t)pl->info.grid_bytes;
     if (what == Out::Spread) {
         e = hipMemcpyAsync(o1, w.grid, gbytes, hipMemcpyDeviceToDevice, s);
         return e == hipSuccess ? EWALD_OK : hip_fail(e, "grid copy");
     }
-    if ((e = launch_fgc(*pl, w, s, true, true, st)) != hipSuccess) return hip_fail(e, "FFT/CNV/IFFT");
+    if ((e = launch_fgc(*pl, w, s, true, true, st, nsys)) != hipSuccess) return hip_fail(e, "FFT/CNV/IFFT");
     mark(4);
     if (what == Out::FarGrid) {
         e = hipMemcpyAsync(o1, w.grid, gbytes, hipMemcpyDeviceToDevice, s);
@@ -728,9 +765,9 @@ int run(ewald_plan_t plan, int64_t n64, const double* x, const double* f, void* 
     }
     if (near && (e = hipStreamWaitEvent(s, join, 0)) != hipSuccess) return hip_fail(e, "join wait");
     if (what == Out::Full)
-        e = launch_g2p(*pl, w, n, f, (double*)o1, nullptr, nullptr, s);
+        e = launch_g2p(*pl, w, n, f, (double*)o1, nullptr, nullptr, *batch, s);
     else
-        e = launch_g2p(*pl, w, n, f, nullptr, (double*)o1, (double*)o2, s);
+        e = launch_g2p(*pl, w, n, f, nullptr, (double*)o1, (double*)o2, *batch, s);
     if (e != hipSuccess) return hip_fail(e, "G2P");
     mark(5);
     if (t) {
@@ -842,6 +879,26 @@ int ewald_eval_overlap(ewald_plan_t plan, int64_t n, const double* x, const doub
     if (n > 0 && near_stream == stream) return fail(EWALD_EINVAL, "the near-field stream must differ from the stream");
     return run(plan, n, x, f, u, u, workspace, workspace_bytes, stream, Out::Full, false, nullptr, nullptr, 0,
                (hipStream_t)near_stream, (hipEvent_t)fork_event, (hipEvent_t)join_event);
+}
+
+int64_t ewald_workspace_bytes_batch(ewald_plan_t plan, int32_t count, const int64_t* offsets)
+{
+    if (!plan) return fail(EWALD_EINVAL, "null plan");
+    Batch b;
+    const int rc = make_batch(reinterpret_cast<Plan*>(plan), count, offsets, &b);
+    if (rc != EWALD_OK) return rc;
+    return layout_work(*reinterpret_cast<Plan*>(plan), offsets[count], nullptr, nullptr, count);
+}
+
+int ewald_eval_batch(ewald_plan_t plan, int32_t count, const int64_t* offsets, const double* x, const double* f,
+                     double* u, void* workspace, int64_t workspace_bytes, void* stream)
+{
+    if (!plan) return fail(EWALD_EINVAL, "null plan");
+    Batch b;
+    const int rc = make_batch(reinterpret_cast<Plan*>(plan), count, offsets, &b);
+    if (rc != EWALD_OK) return rc;
+    return run(plan, offsets[count], x, f, u, u, workspace, workspace_bytes, stream, Out::Full, false, nullptr,
+               nullptr, 0, nullptr, nullptr, nullptr, &b);
 }
 
 int ewald_eval_parts(ewald_plan_t plan, int64_t n, const double* x, const double* f, double* u_near,

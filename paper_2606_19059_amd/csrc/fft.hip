@@ -234,6 +234,7 @@ __global__ __launch_bounds__(256) void k_fft_x_cnv(T* __restrict__ grid, int64_t
     const int per = M1 * ncols;  // elements per component (power of two)
     C2<T>* a = reinterpret_cast<C2<T>*>(smem_raw);
     C2<T>* b = a + (size_t)3 * per;
+    grid += (int64_t)blockIdx.y * 3 * ncells;  // system blockIdx.y of a batch
     const int tiles_per_y = H / ncols;
     const int ky = blockIdx.x / tiles_per_y;
     const int kz0 = (blockIdx.x - ky * tiles_per_y) * ncols;
@@ -362,7 +363,7 @@ inline int pow2_floor(int v)
 }
 
 template <typename T>
-hipError_t launch_fgc_t(const Plan& pl, const Work& w, hipStream_t s, bool inverse_too, bool cnv, bool st)
+hipError_t launch_fgc_t(const Plan& pl, const Work& w, hipStream_t s, bool inverse_too, bool cnv, bool st, int nsys)
 {
     const Geometry& g = pl.g;
     const int M1 = g.M[0], M2 = g.M[1], M3 = g.M[2], H = M3 / 2;
@@ -380,7 +381,9 @@ hipError_t launch_fgc_t(const Plan& pl, const Work& w, hipStream_t s, bool inver
     int ncz = pow2_floor(max(1, budget / H));
     if (ncz > nlines) ncz = pow2_floor(nlines);
     size_t shz = 2 * (size_t)H * (ncz + 1) * sizeof(C2<T>);  // rows padded by one element
-    const int ncomp_in = st ? 9 : 3;  // forward transforms: force (+ stresslet tensor)
+    // forward transforms: force (+ stresslet tensor); the systems of a batch hold consecutive
+    // groups of 3 grid components
+    const int ncomp_in = st ? 9 : 3 * nsys;
     dim3 gz((nlines + ncz - 1) / ncz, ncomp_in);
     hipLaunchKernelGGL((k_fft_z<T>), gz, dim3(256), shz, s, grid, nc, nlines, H, ncz, -1, twh, twf);
     // pass 2: y forward
@@ -389,7 +392,8 @@ hipError_t launch_fgc_t(const Plan& pl, const Work& w, hipStream_t s, bool inver
     size_t shy = 2 * (size_t)M2 * ncy * sizeof(C2<T>);
     dim3 gy(M1 * (H / ncy), ncomp_in);
     hipLaunchKernelGGL((k_fft_y<T>), gy, dim3(256), shy, s, grid, nc, M2, H, ncy, -1, tw1);
-    gy.y = 3;  // the inverse transforms carry the 3 velocity components
+    gy.y = 3 * nsys;  // the inverse transforms carry the 3 velocity components
+    gz.y = 3 * nsys;
     // pass 3: x forward + CNV (+ inverse)
     int ncx = pow2_floor(max(1, budget / (3 * M1)));
     if (ncx > H) ncx = H;
@@ -411,8 +415,8 @@ hipError_t launch_fgc_t(const Plan& pl, const Work& w, hipStream_t s, bool inver
             hipLaunchKernelGGL((k_cnv_st_x<T>), dim3(M2 * (H / ncx)), dim3(256), shx, s, grid, nc, M1, M2, H, ncx,
                                tw0, ca);
     } else {
-        hipLaunchKernelGGL((k_fft_x_cnv<T>), dim3(M2 * (H / ncx)), dim3(256), shx, s, grid, nc, M1, M2, H, ncx,
-                           cnv ? 1 : 0, inverse_too ? 1 : 0, tw0, ca);
+        hipLaunchKernelGGL((k_fft_x_cnv<T>), dim3(M2 * (H / ncx), nsys), dim3(256), shx, s, grid, nc, M1, M2, H,
+                           ncx, cnv ? 1 : 0, inverse_too ? 1 : 0, tw0, ca);
     }
     if (inverse_too) {
         hipLaunchKernelGGL((k_fft_y<T>), gy, dim3(256), shy, s, grid, nc, M2, H, ncy, +1, tw1);
@@ -423,10 +427,10 @@ hipError_t launch_fgc_t(const Plan& pl, const Work& w, hipStream_t s, bool inver
 
 }  // namespace
 
-hipError_t launch_fgc(const Plan& pl, const Work& w, hipStream_t s, bool inverse_too, bool cnv, bool st)
+hipError_t launch_fgc(const Plan& pl, const Work& w, hipStream_t s, bool inverse_too, bool cnv, bool st, int nsys)
 {
-    if (pl.grid64) return launch_fgc_t<double>(pl, w, s, inverse_too, cnv, st);
-    return launch_fgc_t<float>(pl, w, s, inverse_too, cnv, st);
+    if (pl.grid64) return launch_fgc_t<double>(pl, w, s, inverse_too, cnv, st, nsys);
+    return launch_fgc_t<float>(pl, w, s, inverse_too, cnv, st, nsys);
 }
 
 }  // namespace ewald

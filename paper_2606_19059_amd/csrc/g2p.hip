@@ -55,7 +55,7 @@ __global__ __launch_bounds__(64) void k_g2p(int n, const typename RecView<T>::Re
                                             double self_coef, const double* __restrict__ u_near,
                                             const double* __restrict__ f_in, double* __restrict__ u,
                                             double* __restrict__ u_near_out,
-                                            double* __restrict__ u_far_out)
+                                            double* __restrict__ u_far_out, Batch bt)
 {
     // lane items: (footprint row y, run of V consecutive z) -- one 16-byte (8-byte for FP32
     // grids with P not a multiple of 4) load per item and x-plane
@@ -78,9 +78,6 @@ __global__ __launch_bounds__(64) void k_g2p(int n, const typename RecView<T>::Re
     const int64_t nc = g.ncells;
     // 32-bit offsets within one component (at most 512^3 points)
     const unsigned plane = (unsigned)M2 * (unsigned)M3;
-    const TG* __restrict__ g0 = grid;
-    const TG* __restrict__ g1 = grid + nc;
-    const TG* __restrict__ g2 = grid + 2 * nc;
     const int64_t nn = n;
     const T e2 = exp((T)-2 * wa.beta);  // ratio of consecutive Gaussian recurrence factors
     const int s0 = xcd_remap((int)blockIdx.x, (int)gridDim.x) * kG2PGroup;
@@ -123,6 +120,10 @@ __global__ __launch_bounds__(64) void k_g2p(int n, const typename RecView<T>::Re
         }
         __syncthreads();
         const int ax = anc[q][0], ay = anc[q][1], az = anc[q][2];
+        // the grid of the target's system (the systems of a batch are consecutive sorted ranges)
+        const TG* __restrict__ g0 = grid + (int64_t)3 * batch_system(bt, min(sg + q, s1 - 1)) * nc;
+        const TG* __restrict__ g1 = g0 + nc;
+        const TG* __restrict__ g2 = g0 + 2 * nc;
         double a0 = 0, a1 = 0, a2 = 0;  // FP64 sums in every mode (see below)
 #pragma unroll 1
         for (int pass = 0; pass < kPass; ++pass) {
@@ -208,28 +209,28 @@ __global__ __launch_bounds__(64) void k_g2p(int n, const typename RecView<T>::Re
 
 template <typename T, typename TG, int P>
 hipError_t launch_g2p_t(const Plan& pl, const Work& w, int n, const double* f, double* u, double* un,
-                        double* uf, hipStream_t s)
+                        double* uf, const Batch& b, hipStream_t s)
 {
-    const double self_coef = 4.0 * pl.xi / sqrt(M_PI);
+    const double self_coef = pl.info.self_coef;
     constexpr int per_wave = g2p_per_wave<TG>();
     hipLaunchKernelGGL((k_g2p<T, TG, P>), dim3((n + per_wave - 1) / per_wave), dim3(kWave), 0, s, n,
                        (const typename RecView<T>::Rec*)w.rec, (const TG*)w.grid, pl.g, make_win_args<T>(pl),
-                       self_coef, w.u_near, f, u, un, uf);
+                       self_coef, w.u_near, f, u, un, uf, b);
     return hipGetLastError();
 }
 
 template <typename T, typename TG>
 hipError_t launch_g2p_p(const Plan& pl, const Work& w, int n, const double* f, double* u, double* un,
-                        double* uf, hipStream_t s)
+                        double* uf, const Batch& b, hipStream_t s)
 {
     switch (pl.P) {
-    case 4: return launch_g2p_t<T, TG, 4>(pl, w, n, f, u, un, uf, s);
-    case 6: return launch_g2p_t<T, TG, 6>(pl, w, n, f, u, un, uf, s);
-    case 8: return launch_g2p_t<T, TG, 8>(pl, w, n, f, u, un, uf, s);
-    case 10: return launch_g2p_t<T, TG, 10>(pl, w, n, f, u, un, uf, s);
-    case 12: return launch_g2p_t<T, TG, 12>(pl, w, n, f, u, un, uf, s);
-    case 14: return launch_g2p_t<T, TG, 14>(pl, w, n, f, u, un, uf, s);
-    case 16: return launch_g2p_t<T, TG, 16>(pl, w, n, f, u, un, uf, s);
+    case 4: return launch_g2p_t<T, TG, 4>(pl, w, n, f, u, un, uf, b, s);
+    case 6: return launch_g2p_t<T, TG, 6>(pl, w, n, f, u, un, uf, b, s);
+    case 8: return launch_g2p_t<T, TG, 8>(pl, w, n, f, u, un, uf, b, s);
+    case 10: return launch_g2p_t<T, TG, 10>(pl, w, n, f, u, un, uf, b, s);
+    case 12: return launch_g2p_t<T, TG, 12>(pl, w, n, f, u, un, uf, b, s);
+    case 14: return launch_g2p_t<T, TG, 14>(pl, w, n, f, u, un, uf, b, s);
+    case 16: return launch_g2p_t<T, TG, 16>(pl, w, n, f, u, un, uf, b, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -237,12 +238,12 @@ hipError_t launch_g2p_p(const Plan& pl, const Work& w, int n, const double* f, d
 }  // namespace
 
 hipError_t launch_g2p(const Plan& pl, const Work& w, int n, const double* f, double* u,
-                      double* u_near_out, double* u_far_out, hipStream_t s)
+                      double* u_near_out, double* u_far_out, const Batch& b, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    if (pl.mode == EWALD_FP64) return launch_g2p_p<double, double>(pl, w, n, f, u, u_near_out, u_far_out, s);
-    if (pl.grid64) return launch_g2p_p<float, double>(pl, w, n, f, u, u_near_out, u_far_out, s);
-    return launch_g2p_p<float, float>(pl, w, n, f, u, u_near_out, u_far_out, s);
+    if (pl.mode == EWALD_FP64) return launch_g2p_p<double, double>(pl, w, n, f, u, u_near_out, u_far_out, b, s);
+    if (pl.grid64) return launch_g2p_p<float, double>(pl, w, n, f, u, u_near_out, u_far_out, b, s);
+    return launch_g2p_p<float, float>(pl, w, n, f, u, u_near_out, u_far_out, b, s);
 }
 
 }  // namespace ewald

@@ -20,9 +20,31 @@ struct Geometry {
     int log2B;
     int NT[3];        // tiles per dimension (M / B)
     int S[3];         // P2P stencil half-width in tiles
-    int ncells;       // M1 M2 M3 (sort bins = grid cells)
-    int ntiles;       // NT1 NT2 NT3
+    int ncells;       // M1 M2 M3 (sort bins = grid cells) of one system
+    int ntiles;       // NT1 NT2 NT3 of one system
+    int nsys;         // independent systems evaluated together (1, or a batch's count): system r
+                      // owns cells [r ncells, (r + 1) ncells) of the cell list, tiles
+                      // [r ntiles, (r + 1) ntiles) and grid components [3 r, 3 r + 3)
 };
+
+// Particle ranges of the systems of one evaluation: system r owns particles [off[r], off[r + 1])
+// of the input arrays (and, after the sort, of the sorted order).  Passed by value to kernels.
+constexpr int kMaxBatch = EWALD_MAX_BATCH;
+struct Batch {
+    int count;
+    int off[kMaxBatch + 1];
+};
+
+// system of particle (or sorted slot) i: the last r with off[r] <= i
+__host__ __device__ inline int batch_system(const Batch& b, int i)
+{
+    int lo = 0, hi = b.count;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (b.off[mid] <= i) lo = mid; else hi = mid;
+    }
+    return lo;
+}
 
 // Interleave the bits of x (odd positions) and y (even positions), 4 bits each.
 __host__ __device__ inline int morton2(int x, int y)
@@ -113,7 +135,8 @@ struct Work {
     int64_t bytes;
 };
 
-int64_t layout_work(const Plan& pl, int64_t n, char* base, Work* w);
+// workspace layout for n particles in `nsys` systems (a batch) of this plan
+int64_t layout_work(const Plan& pl, int64_t n, char* base, Work* w, int nsys = 1);
 // doubles of P2G's segment-boundary buffer for this plan (0: the sweep uses no halo)
 int64_t p2g_halo_elems(const Plan& pl);
 // length of the x-segments of P2G's sweep (a power of two dividing M[0])
@@ -121,17 +144,19 @@ int p2g_segment_length(const int M[3], int P);
 
 // Launchers (all enqueue on `s`, return hipSuccess or the launch error).
 hipError_t launch_sort(const Plan& pl, const Work& w, int n, const double* x, const double* f,
-                       hipStream_t s);
+                       const Batch& b, hipStream_t s);
 // `st`: this evaluation has stresslet sources (w.srec filled, 9 grid components)
 hipError_t launch_gather_st(const Plan& pl, const Work& w, int n, const double* q, const double* nrm,
                             hipStream_t s);
-hipError_t launch_p2p(const Plan& pl, const Work& w, int n, hipStream_t s, bool st);
+hipError_t launch_p2p(const Plan& pl, const Work& w, int n, hipStream_t s, bool st, int nsys = 1);
 // exact number of ordered pairs (i != j, all images) with 0 < |r| < r_c, written to *count
-hipError_t launch_count_pairs(const Plan& pl, const Work& w, int n, unsigned long long* count, hipStream_t s);
-hipError_t launch_p2g(const Plan& pl, const Work& w, int n, hipStream_t s, bool st);
-hipError_t launch_fgc(const Plan& pl, const Work& w, hipStream_t s, bool inverse_too, bool cnv, bool st);
+hipError_t launch_count_pairs(const Plan& pl, const Work& w, int n, unsigned long long* count, hipStream_t s,
+                              int nsys = 1);
+hipError_t launch_p2g(const Plan& pl, const Work& w, int n, hipStream_t s, bool st, int nsys = 1);
+hipError_t launch_fgc(const Plan& pl, const Work& w, hipStream_t s, bool inverse_too, bool cnv, bool st,
+                      int nsys = 1);
 hipError_t launch_g2p(const Plan& pl, const Work& w, int n, const double* f, double* u,
-                      double* u_near_out, double* u_far_out, hipStream_t s);
+                      double* u_near_out, double* u_far_out, const Batch& b, hipStream_t s);
 hipError_t launch_fill_i32(int* p, int64_t count, int value, hipStream_t s);
 // *out (= 0 first when `reset`) += number of non-finite values among a[0..count)
 hipError_t launch_count_nonfinite(const double* a, int64_t count, int* out, hipStream_t s, bool reset = true);

@@ -54,8 +54,13 @@ __global__ __launch_bounds__(kWaves * 64) void k_p2g_sweep(const typename RecVie
                                                            const int* __restrict__ start, Geometry g,
                                                            WinArgs<T> wa, int seg, int npy, int npz,
                                                            const double* __restrict__ sv, int sv_off,
-                                                           TG* __restrict__ grid, double* __restrict__ halo)
+                                                           TG* __restrict__ grid, double* __restrict__ halo,
+                                                           int64_t grid_stride, int64_t halo_stride)
 {
+    // system blockIdx.y of a batch: its cell list, grid and halo planes
+    start += (int64_t)blockIdx.y * g.ncells;
+    grid += (int64_t)blockIdx.y * grid_stride;
+    if (halo) halo += (int64_t)blockIdx.y * halo_stride;
     constexpr int W = kPatch + P - 1;
     __shared__ int run_start[kMaxRuns];
     __shared__ int run_pre[kMaxRuns + 1];
@@ -305,8 +310,11 @@ __global__ __launch_bounds__(kWaves * 64) void k_p2g_sweep(const typename RecVie
 // [segment][k][component][line].
 template <typename TG>
 __global__ __launch_bounds__(256) void k_p2g_halo_sum(const double* __restrict__ halo, int nseg, int seg, int P,
-                                                      Geometry g, TG* __restrict__ grid)
+                                                      Geometry g, TG* __restrict__ grid, int64_t grid_stride,
+                                                      int64_t halo_stride)
 {
+    halo += (int64_t)blockIdx.y * halo_stride;
+    grid += (int64_t)blockIdx.y * grid_stride;
     const int64_t m23 = (int64_t)g.M[1] * g.M[2];
     const int64_t planes = (int64_t)nseg * (P - 1) * 3;
     const int64_t total = planes * m23;
@@ -323,7 +331,7 @@ __global__ __launch_bounds__(256) void k_p2g_halo_sum(const double* __restrict__
 
 
 template <typename TG, int P>
-hipError_t launch_p2g_t(const Plan& pl, const Work& w, hipStream_t s, bool st)
+hipError_t launch_p2g_t(const Plan& pl, const Work& w, hipStream_t s, bool st, int nsys)
 {
     const Geometry& g = pl.g;
     const int npy = g.M[1] / kPatch, npz = g.M[2] / kPatch;
@@ -336,29 +344,30 @@ hipError_t launch_p2g_t(const Plan& pl, const Work& w, hipStream_t s, bool st)
     const int fix_blocks = (int)std::min<int64_t>((halo_n + 255) / 256, 4096);
     // force (3 components); with stresslet sources also the 6 tensor components, three per sweep
     const int passes = st ? 3 : 1;
+    const int64_t gstride = (int64_t)(st ? 9 : 3) * g.ncells, hstride = p2g_halo_elems(pl);
     for (int ps = 0; ps < passes; ++ps) {
         TG* grid = (TG*)w.grid + (int64_t)3 * ps * g.ncells;
-        hipLaunchKernelGGL((k_p2g_sweep<double, TG, P>), dim3(blocks), dim3(kWaves * kWave), 0, s,
+        hipLaunchKernelGGL((k_p2g_sweep<double, TG, P>), dim3(blocks, nsys), dim3(kWaves * kWave), 0, s,
                            (const Rec64*)w.rec, w.start, g, make_win_args<double>(pl), seg, npy, npz,
-                           ps == 0 ? nullptr : w.srec, 3 * (ps - 1), grid, halo);
+                           ps == 0 ? nullptr : w.srec, 3 * (ps - 1), grid, halo, gstride, hstride);
         if (halo)
-            hipLaunchKernelGGL((k_p2g_halo_sum<TG>), dim3(fix_blocks), dim3(256), 0, s, (const double*)halo, nseg,
-                               seg, P, g, grid);
+            hipLaunchKernelGGL((k_p2g_halo_sum<TG>), dim3(fix_blocks, nsys), dim3(256), 0, s, (const double*)halo,
+                               nseg, seg, P, g, grid, gstride, hstride);
     }
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_p2g_p(const Plan& pl, const Work& w, hipStream_t s, bool st)
+hipError_t launch_p2g_p(const Plan& pl, const Work& w, hipStream_t s, bool st, int nsys)
 {
     switch (pl.P) {
-    case 4: return launch_p2g_t<T, 4>(pl, w, s, st);
-    case 6: return launch_p2g_t<T, 6>(pl, w, s, st);
-    case 8: return launch_p2g_t<T, 8>(pl, w, s, st);
-    case 10: return launch_p2g_t<T, 10>(pl, w, s, st);
-    case 12: return launch_p2g_t<T, 12>(pl, w, s, st);
-    case 14: return launch_p2g_t<T, 14>(pl, w, s, st);
-    case 16: return launch_p2g_t<T, 16>(pl, w, s, st);
+    case 4: return launch_p2g_t<T, 4>(pl, w, s, st, nsys);
+    case 6: return launch_p2g_t<T, 6>(pl, w, s, st, nsys);
+    case 8: return launch_p2g_t<T, 8>(pl, w, s, st, nsys);
+    case 10: return launch_p2g_t<T, 10>(pl, w, s, st, nsys);
+    case 12: return launch_p2g_t<T, 12>(pl, w, s, st, nsys);
+    case 14: return launch_p2g_t<T, 14>(pl, w, s, st, nsys);
+    case 16: return launch_p2g_t<T, 16>(pl, w, s, st, nsys);
     default: return hipErrorInvalidValue;
     }
 }
@@ -385,11 +394,11 @@ int64_t p2g_halo_elems(const Plan& pl)
     return 2 * (int64_t)(pl.g.M[0] / seg) * (pl.P - 1) * 3 * pl.g.M[1] * pl.g.M[2];
 }
 
-hipError_t launch_p2g(const Plan& pl, const Work& w, int n, hipStream_t s, bool st)
+hipError_t launch_p2g(const Plan& pl, const Work& w, int n, hipStream_t s, bool st, int nsys)
 {
     (void)n;
-    if (pl.grid64) return launch_p2g_p<double>(pl, w, s, st);
-    return launch_p2g_p<float>(pl, w, s, st);
+    if (pl.grid64) return launch_p2g_p<double>(pl, w, s, st, nsys);
+    return launch_p2g_p<float>(pl, w, s, st, nsys);
 }
 
 }  // namespace ewald

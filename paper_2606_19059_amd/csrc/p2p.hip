@@ -295,11 +295,11 @@ __global__ __launch_bounds__(64) void k_p2p(int n, const Rec64* __restrict__ rec
     // measured 12% slower here, unlike in G2P
     const int wave = uniform_i((int)blockIdx.x);
     const int lane = threadIdx.x;
-    const int total = chunk_off[g.ntiles];
+    const int total = chunk_off[g.ntiles * g.nsys];  // chunks of all systems
     if (wave >= total) return;
 
     // tile of this wave: largest t with chunk_off[t] <= wave
-    int lo = 0, hi = g.ntiles;
+    int lo = 0, hi = g.ntiles * g.nsys;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         if (chunk_off[mid] <= wave) lo = mid; else hi = mid;
@@ -312,7 +312,9 @@ __global__ __launch_bounds__(64) void k_p2p(int n, const Rec64* __restrict__ rec
     const bool active = i < t_end;
     const Rec64 me = rec[active ? i : first];
 
-    const int tc[3] = {t / (g.NT[1] * g.NT[2]), (t / g.NT[2]) % g.NT[1], t % g.NT[2]};
+    // tile t of system sys (the systems of a batch have consecutive tile ranges)
+    const int sys = t / g.ntiles, tl = t - sys * g.ntiles, tbase = sys * g.ntiles;
+    const int tc[3] = {tl / (g.NT[1] * g.NT[2]), (tl / g.NT[2]) % g.NT[1], tl % g.NT[2]};
     double w[3], blo[3], bhi[3], tx[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -387,7 +389,7 @@ __global__ __launch_bounds__(64) void k_p2p(int n, const Rec64* __restrict__ rec
                 const double shz = fz * g.L[2];
                 const double gz = fmax(0.0, fmax(uz * w[2] - bhi[2], blo[2] - (uz + 1) * w[2]));
                 if (gx * gx + gy * gy + gz * gz >= a.rc2) continue;
-                const int nt = (wx * g.NT[1] + wy) * g.NT[2] + wz;
+                const int nt = tbase + (wx * g.NT[1] + wy) * g.NT[2] + wz;
                 const int sa = start[nt * per], sb = start[(nt + 1) * per];
                 for (int base = sa; base < sb; base += kWave) {
                     const int s = base + lane;
@@ -519,10 +521,10 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
     const int wave = uniform_i((int)blockIdx.x) / nsplit;
     const int part = uniform_i((int)blockIdx.x) % nsplit;
     const int lane = threadIdx.x;
-    const int total = chunk_off[g.ntiles];
+    const int total = chunk_off[g.ntiles * g.nsys];  // chunks of all systems
     if (wave >= total) return;
 
-    int lo = 0, hi = g.ntiles;
+    int lo = 0, hi = g.ntiles * g.nsys;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         if (chunk_off[mid] <= wave) lo = mid; else hi = mid;
@@ -535,7 +537,9 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
     const bool active = i < t_end;
     const Rec64 me = rec[active ? i : first];
 
-    const int tc[3] = {t / (g.NT[1] * g.NT[2]), (t / g.NT[2]) % g.NT[1], t % g.NT[2]};
+    // tile t of system sys (the systems of a batch have consecutive tile ranges)
+    const int sys = t / g.ntiles, tl = t - sys * g.ntiles, tbase = sys * g.ntiles;
+    const int tc[3] = {tl / (g.NT[1] * g.NT[2]), (tl / g.NT[2]) % g.NT[1], tl % g.NT[2]};
     double w[3], blo[3], bhi[3], tx[3], oacc[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -741,7 +745,7 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
                 if (gx * gx + gy * gy + gz * gz >= a.rc2) continue;
                 if (tk++ % nsplit != part) continue;  // another wave of this chunk takes it
                 const bool own = (dx == 0 && dy == 0 && dz == 0);
-                const int nt = (wx * g.NT[1] + wy) * g.NT[2] + wz;
+                const int nt = tbase + (wx * g.NT[1] + wy) * g.NT[2] + wz;
                 // own tile: sources below the first target can pair with none of them
                 const int sa = own ? first : start[nt * per], sb = start[(nt + 1) * per];
                 const int koff = own ? 0 : kFar;
@@ -835,24 +839,29 @@ __global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
 
 }  // namespace
 
-hipError_t launch_count_pairs(const Plan& pl, const Work& w, int n, unsigned long long* count, hipStream_t s)
+hipError_t launch_count_pairs(const Plan& pl, const Work& w, int n, unsigned long long* count, hipStream_t s,
+                              int nsys)
 {
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, count);
     if (n > 0) {
         const PairArgs a = pair_args(pl);
-        const int64_t waves = (int64_t)pl.g.ntiles + (n + kWave - 1) / kWave;
+        Geometry g = pl.g;
+        g.nsys = nsys;
+        const int64_t waves = (int64_t)g.ntiles * nsys + (n + kWave - 1) / kWave;
         hipLaunchKernelGGL((k_p2p<double, double, false, true>), dim3((unsigned)waves), dim3(kWave), 0, s, n,
-                           (const Rec64*)w.rec, w.start, w.chunk_off, pl.g, a, nullptr, count);
+                           (const Rec64*)w.rec, w.start, w.chunk_off, g, a, nullptr, count);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_p2p(const Plan& pl, const Work& w, int n, hipStream_t s, bool st)
+hipError_t launch_p2p(const Plan& pl, const Work& w, int n, hipStream_t s, bool st, int nsys)
 {
     if (n <= 0) return hipSuccess;
     const PairArgs a = pair_args(pl);
+    Geometry g = pl.g;
+    g.nsys = nsys;
     const bool fast = pl.p.tol >= 1e-10;
-    const int64_t waves = (int64_t)pl.g.ntiles + (n + kWave - 1) / kWave;
+    const int64_t waves = (int64_t)g.ntiles * nsys + (n + kWave - 1) / kWave;
     const dim3 grid((unsigned)waves), block(kWave);
     const Rec64* rec = (const Rec64*)w.rec;
     const bool f64 = pl.mode == EWALD_FP64;
@@ -861,13 +870,13 @@ hipError_t launch_p2p(const Plan& pl, const Work& w, int n, hipStream_t s, bool 
         // gfx950, those of FP32 are not (measured: 3x slower kernel)
         if (f64 && fast)
             hipLaunchKernelGGL((k_p2p<double, double, true>), grid, block, 0, s, n, rec, w.start, w.chunk_off,
-                               pl.g, a, w.u_near);
+                               g, a, w.u_near);
         else if (f64)
             hipLaunchKernelGGL((k_p2p<double, double, false>), grid, block, 0, s, n, rec, w.start, w.chunk_off,
-                               pl.g, a, w.u_near);
+                               g, a, w.u_near);
         else
             hipLaunchKernelGGL((k_p2p<float, double, false>), grid, block, 0, s, n, rec, w.start, w.chunk_off,
-                               pl.g, a, w.u_near);
+                               g, a, w.u_near);
         return hipGetLastError();
     }
     // Symmetric kernel: with few chunks per wave slot of the chip (c2: 15.6k chunks, about 4 per
@@ -882,24 +891,24 @@ hipError_t launch_p2p(const Plan& pl, const Work& w, int n, hipStream_t s, bool 
     if (st) {
         if (f64 && fast)
             hipLaunchKernelGGL((k_p2p_sym<double, true, true>), sgrid, block, 0, s, n, rec, sr, w.start, w.chunk_off,
-                               pl.g, a, w.u_near, kSplit);
+                               g, a, w.u_near, kSplit);
         else if (f64)
             hipLaunchKernelGGL((k_p2p_sym<double, false, true>), sgrid, block, 0, s, n, rec, sr, w.start,
-                               w.chunk_off, pl.g, a, w.u_near, kSplit);
+                               w.chunk_off, g, a, w.u_near, kSplit);
         else
             hipLaunchKernelGGL((k_p2p_sym<float, false, true>), sgrid, block, 0, s, n, rec, sr, w.start,
-                               w.chunk_off, pl.g, a, w.u_near, kSplit);
+                               w.chunk_off, g, a, w.u_near, kSplit);
         return hipGetLastError();
     }
     if (f64 && fast)
         hipLaunchKernelGGL((k_p2p_sym<double, true, false>), sgrid, block, 0, s, n, rec, sr, w.start, w.chunk_off,
-                           pl.g, a, w.u_near, kSplit);
+                           g, a, w.u_near, kSplit);
     else if (f64)
         hipLaunchKernelGGL((k_p2p_sym<double, false, false>), sgrid, block, 0, s, n, rec, sr, w.start,
-                           w.chunk_off, pl.g, a, w.u_near, kSplit);
+                           w.chunk_off, g, a, w.u_near, kSplit);
     else
         hipLaunchKernelGGL((k_p2p_sym<float, false, false>), sgrid, block, 0, s, n, rec, sr, w.start,
-                           w.chunk_off, pl.g, a, w.u_near, kSplit);
+                           w.chunk_off, g, a, w.u_near, kSplit);
     return hipGetLastError();
 }
 

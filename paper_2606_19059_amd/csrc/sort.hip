@@ -38,8 +38,9 @@ __device__ inline void cell_of(double x, double L, double h, int M, int& c, doub
     t = s - (double)ci;
 }
 
+// key = system * ncells + cell key: the systems of a batch occupy consecutive key ranges
 __global__ void k_bin(int n, const double* __restrict__ x, Geometry g, int* __restrict__ key,
-                      int* __restrict__ count)
+                      int* __restrict__ count, Batch b)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -47,7 +48,7 @@ __global__ void k_bin(int n, const double* __restrict__ x, Geometry g, int* __re
     double t, wx;
 #pragma unroll
     for (int d = 0; d < 3; ++d) cell_of(x[(int64_t)d * n + i], g.L[d], g.h[d], g.M[d], c[d], t, wx);
-    const int k = cell_key(c[0], c[1], c[2], g);
+    const int k = batch_system(b, i) * g.ncells + cell_key(c[0], c[1], c[2], g);
     key[i] = k;
     atomicAdd(&count[k], 1);
 }
@@ -262,11 +263,11 @@ __global__ void k_gather_st(int n, const double* __restrict__ q, const double* _
     o[5] = 0.5 * (q1 * n2 + q2 * n1);
 }
 
-// Number of 64-target waves per P2P tile.
+// Number of 64-target waves per P2P tile (the tiles of all systems).
 __global__ void k_tile_chunks(Geometry g, const int* __restrict__ start, int* __restrict__ chunks)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= g.ntiles) return;
+    if (t >= g.ntiles * g.nsys) return;
     const int per = 1 << (3 * g.log2B);
     const int cnt = start[(t + 1) * per] - start[t * per];
     chunks[t] = (cnt + kWave - 1) / kWave;
@@ -410,22 +411,23 @@ hipError_t launch_exclusive_scan(const int* in, int* out, int count, int* part, 
 }
 
 hipError_t launch_sort(const Plan& pl, const Work& w, int n, const double* x, const double* f,
-                       hipStream_t s)
+                       const Batch& b, hipStream_t s)
 {
-    const Geometry& g = pl.g;
-    hipError_t e = launch_fill_i32(w.count, g.ncells, 0, s);
+    Geometry g = pl.g;
+    g.nsys = b.count;
+    const int ncells = g.ncells * g.nsys, ntiles = g.ntiles * g.nsys;  // over all systems
+    hipError_t e = launch_fill_i32(w.count, ncells, 0, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bin, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, x, g, w.key, w.count);
-    e = launch_exclusive_scan(w.count, w.start, g.ncells, w.part, s);
+    hipLaunchKernelGGL(k_bin, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, x, g, w.key, w.count, b);
+    e = launch_exclusive_scan(w.count, w.start, ncells, w.part, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_copy_i32, dim3(blocks_for(g.ncells, 256)), dim3(256), 0, s, w.start, w.count,
-                       g.ncells);
+    hipLaunchKernelGGL(k_copy_i32, dim3(blocks_for(ncells, 256)), dim3(256), 0, s, w.start, w.count, ncells);
     hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, w.key, w.count, w.perm);
     // per-cell order by original index; the key array is free after the scatter and serves as
     // the merge buffer of the largest cells
     if ((e = launch_fill_i32(w.cell_lists, 2, 0, s)) != hipSuccess) return e;
     const int64_t mid_cap = mid_list_cap(n);
-    hipLaunchKernelGGL(k_cell_order, dim3(blocks_for(g.ncells, 256)), dim3(256), 0, s, g.ncells, w.start,
+    hipLaunchKernelGGL(k_cell_order, dim3(blocks_for(ncells, 256)), dim3(256), 0, s, ncells, w.start,
                        w.perm, w.cell_lists, mid_cap);
     const int mid_blocks = (int)std::min<int64_t>(2048, std::max<int64_t>(1, mid_list_cap(n) / 4));
     hipLaunchKernelGGL(k_sort_mid_cells, dim3(mid_blocks), dim3(256), 0, s, w.start, w.perm, w.cell_lists);
@@ -435,9 +437,9 @@ hipError_t launch_sort(const Plan& pl, const Work& w, int n, const double* x, co
     hipLaunchKernelGGL(k_gather64, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, x, f, w.perm, g,
                        (Rec64*)w.rec);
     // P2P work list: waves per tile, then their offsets
-    hipLaunchKernelGGL(k_tile_chunks, dim3(blocks_for(g.ntiles, 256)), dim3(256), 0, s, g, w.start,
+    hipLaunchKernelGGL(k_tile_chunks, dim3(blocks_for(ntiles, 256)), dim3(256), 0, s, g, w.start,
                        w.count);
-    return launch_exclusive_scan(w.count, w.chunk_off, g.ntiles, w.part, s);
+    return launch_exclusive_scan(w.count, w.chunk_off, ntiles, w.part, s);
 }
 
 hipError_t launch_gather_st(const Plan& pl, const Work& w, int n, const double* q, const double* nrm,

@@ -33,7 +33,7 @@ import time
 
 import numpy as np
 
-from . import EwaldError, Plan
+from . import MAX_BATCH, EwaldError, Plan
 
 _ALIGN = 256
 
@@ -65,6 +65,7 @@ class Job:
     bypassed: int = 0
     dev_start_ms: float = math.nan  # evaluation start / end on the device clock
     dev_end_ms: float = math.nan
+    batch: int = 0                  # requests in the evaluation that served this one
 
     @property
     def latency(self) -> float:
@@ -136,7 +137,7 @@ class Server:
     """Admission by HBM footprint onto a pool of streams, out of one device arena."""
 
     def __init__(self, n_slots: int = 4, hbm_budget: int | None = None, device: str = "cuda:0",
-                 plan_n_max: int = 1 << 30, max_bypass: int = 8):
+                 plan_n_max: int = 1 << 30, max_bypass: int = 8, batching: bool = True):
         import torch
 
         self.device = torch.device(device)
@@ -149,6 +150,7 @@ class Server:
         self.plans: dict = {}
         self.plan_n_max = plan_n_max  # largest request size served
         self.max_bypass = int(max_bypass)
+        self.batching = bool(batching)  # small requests with one plan evaluated together
         self.clock0 = None
         self.ev0 = torch.cuda.Event(enable_timing=True)
         # statistics of the last run()
@@ -156,13 +158,18 @@ class Server:
         self.in_flight_bytes = 0
         self.memory_waits = 0
         self.bypasses = 0
+        self.batches = 0  # evaluations launched in the last run() (a batch of small requests is one)
 
     # -- plans and footprints -------------------------------------------------------------
 
+    SMALL_N = 16384  # requests up to this size share one plan per (box, tol) and are batched
+
     @staticmethod
     def size_class(n: int) -> int:
-        """Plans are shared by requests whose n rounds up to the same power of two (>= 1024)."""
-        return max(1024, 1 << max(0, int(n) - 1).bit_length())
+        """Plans are shared by requests whose n rounds up to the same power of two; every
+        request of up to SMALL_N particles is in the smallest class (so that small requests
+        with the same box and tolerance can be evaluated together in one batch)."""
+        return max(Server.SMALL_N, 1 << max(0, int(n) - 1).bit_length())
 
     def _key(self, job):
         return (tuple(float(b) for b in job.box), float(job.tol), job.precision, self.size_class(job.n))
@@ -181,10 +188,16 @@ class Server:
             self.plans[key] = pl
         return pl
 
-    def layout(self, job):
-        """Byte offsets of the request's block: workspace, then x, f, u ((3, n) float64 each)."""
-        ws = _round_up(self.plan_for(job).workspace_bytes(job.n))
-        arr = _round_up(24 * job.n)
+    def layout(self, group):
+        """Byte offsets of a group's block (one request, or small requests sharing a plan):
+        workspace, then x, f, u ((3, N) float64 each, the requests' columns side by side)."""
+        if not isinstance(group, (list, tuple)):
+            group = [group]
+        pl = self.plan_for(group[0])
+        n = sum(j.n for j in group)
+        wsb = pl.workspace_bytes(n) if len(group) == 1 else pl.workspace_bytes_batch([j.n for j in group])
+        ws = _round_up(wsb)
+        arr = _round_up(24 * n)
         return ws, arr, ws + 3 * arr
 
     def footprint(self, job) -> int:
@@ -220,56 +233,84 @@ class Server:
     def now(self):
         return time.perf_counter() - self.clock0
 
-    def _admit(self, job, slot, off):
+    def _admit(self, group, slot, off, total):
+        """Enqueue a group on a slot's stream: copies in, one evaluation (ewald_eval_batch for
+        several small requests), copies out.  Returns the requests that failed to enqueue."""
         import torch
 
-        pl = self.plan_for(job)
-        ws_b, arr_b, total = self.layout(job)
+        pl = self.plan_for(group[0])
+        ws_b, arr_b, _ = self.layout(group)
+        n = sum(j.n for j in group)
         blk = self.arena.view(off, total)
         ws = blk[:ws_b]
-        dv = [blk[ws_b + k * arr_b: ws_b + k * arr_b + 24 * job.n].view(torch.float64).view(3, job.n)
-              for k in range(3)]
-        x, f, u = dv
-        job.admitted = self.now()
-        job.slot = slot.idx
-        if job.u is None or tuple(job.u.shape) != (3, job.n) or job.u.is_cuda:
-            job.u = torch.empty((3, job.n), dtype=torch.float64, pin_memory=True)
+        x, f, u = [blk[ws_b + k * arr_b: ws_b + k * arr_b + 24 * n].view(torch.float64).view(3, n) for k in range(3)]
+        cols = []
+        c = 0
+        for j in group:
+            cols.append((c, c + j.n))
+            c += j.n
+            j.admitted = self.now()
+            j.slot = slot.idx
+            j.batch = len(group)
+            if j.u is None or tuple(j.u.shape) != (3, j.n) or j.u.is_cuda:
+                j.u = torch.empty((3, j.n), dtype=torch.float64, pin_memory=True)
         with torch.cuda.stream(slot.stream):
-            x.copy_(job.x, non_blocking=True)
-            f.copy_(job.f, non_blocking=True)
+            for j, (a, b) in zip(group, cols):
+                x[:, a:b].copy_(j.x, non_blocking=True)
+                f[:, a:b].copy_(j.f, non_blocking=True)
             slot.ev_start.record(slot.stream)
             try:
-                pl.eval(x, f, out=u, workspace=ws, stream=slot.stream)
+                if len(group) == 1:
+                    pl.eval(x, f, out=u, workspace=ws, stream=slot.stream)
+                else:
+                    pl.eval_batch(x, f, [j.n for j in group], out=u, workspace=ws, stream=slot.stream)
             except EwaldError as e:
-                # nothing of the evaluation was enqueued: the request fails alone; its block
+                # nothing of the evaluation was enqueued: the group fails alone; its block
                 # returns to the arena once the stream has finished the copies into it
                 slot.ev_done.record(slot.stream)
                 slot.ev_done.synchronize()
                 self.arena.release(off, total)
-                job.error = "evaluation failed: %s" % e
-                job.done = self.now()
-                job.u = None
-                return False
+                for j in group:
+                    j.error = "evaluation failed: %s" % e
+                    j.done = self.now()
+                    j.u = None
+                return list(group)
             slot.ev_end.record(slot.stream)
-            job.u.copy_(u, non_blocking=True)
+            for j, (a, b) in zip(group, cols):
+                j.u.copy_(u[:, a:b], non_blocking=True)
             slot.ev_done.record(slot.stream)
-        slot.job, slot.block = job, (off, total)
+        slot.job, slot.block = list(group), (off, total)
         self.in_flight_bytes += total
         self.max_in_flight_bytes = max(self.max_in_flight_bytes, self.in_flight_bytes)
-        return True
+        return []
 
     def _retire(self, slot):
-        job = slot.job
-        job.done = self.now()
-        job.dev_start_ms = self.ev0.elapsed_time(slot.ev_start)
-        job.dev_end_ms = self.ev0.elapsed_time(slot.ev_end)
-        if job.cancelled:
-            job.error = "cancelled"
-            job.u = None
+        out = []
+        for job in slot.job:
+            job.done = self.now()
+            job.dev_start_ms = self.ev0.elapsed_time(slot.ev_start)
+            job.dev_end_ms = self.ev0.elapsed_time(slot.ev_end)
+            if job.cancelled:
+                job.error = "cancelled"
+                job.u = None
+            out.append(job)
         self.arena.release(*slot.block)
         self.in_flight_bytes -= slot.block[1]
         slot.job, slot.block = None, None
-        return job
+        return out
+
+    def _group(self, ready, lead):
+        """The lead request and, when it is small, the other waiting requests with its plan
+        (up to the library's batch limit), in arrival order."""
+        group = [ready[lead]]
+        if self.batching and ready[lead].n <= self.SMALL_N:
+            key = self._key(ready[lead])
+            for i, j in enumerate(ready):
+                if len(group) >= MAX_BATCH:
+                    break
+                if i != lead and j.n <= self.SMALL_N and self._key(j) == key:
+                    group.append(j)
+        return group
 
     def run(self, jobs, poll_s: float = 2e-5):
         """Serve `jobs` (arrival times in seconds from now); returns every job, served ones
@@ -299,14 +340,14 @@ class Server:
         ready = []
         k = 0
         self.max_in_flight_bytes = self.in_flight_bytes = 0
-        self.memory_waits = self.bypasses = 0
+        self.memory_waits = self.bypasses = self.batches = 0
         self.clock0 = time.perf_counter()
         self.ev0.record(torch.cuda.current_stream(self.device))
         self.ev0.synchronize()
         while k < len(pending) or ready or any(s.job is not None for s in self.slots):
             for s in self.slots:
                 if s.job is not None and s.ev_done.query():
-                    done.append(self._retire(s))
+                    done.extend(self._retire(s))
             t = self.now()
             while k < len(pending) and pending[k].arrival <= t:
                 ready.append(pending[k])
@@ -339,9 +380,25 @@ class Server:
                 if pick is None:
                     self.memory_waits += 1
                     break
-                job = ready.pop(pick)
-                if not self._admit(job, slot, off):
-                    dropped.append(job)
+                # small requests sharing the lead's plan join it in one batched evaluation
+                # while their joint block fits
+                group = self._group(ready, pick)
+                total = ready[pick].footprint
+                if len(group) > 1:
+                    self.arena.release(off, ready[pick].footprint)
+                    while True:
+                        total = self.layout(group)[2]
+                        off = self.arena.alloc(total)
+                        if off is not None or len(group) == 1:
+                            break
+                        group.pop()
+                    if off is None:  # the lead alone fitted a moment ago
+                        total = ready[pick].footprint
+                        off = self.arena.alloc(total)
+                ids = set(id(j) for j in group)
+                ready = [j for j in ready if id(j) not in ids]
+                dropped.extend(self._admit(group, slot, off, total))
+                self.batches += 1
             if poll_s > 0:
                 time.sleep(poll_s)
         return done + dropped
