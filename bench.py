@@ -221,6 +221,21 @@ def serving_leg(n_requests):
     for k, frac in enumerate((0.5, 0.8, 0.95)):
         reset(poisson(frac * rate, 50 + k))
         loads["%.2f" % frac] = keep(serve.summarize(srv.run(jobs)))
+    # small requests only (N log-uniform in [1e3, 1e4]), all waiting: evaluated one by one on the
+    # 4 streams, and grouped by plan into batched evaluations (ewald_eval_batch)
+    sjobs = serve.make_jobs(W.serving_stream(256, rate_per_s=0.0, seed=7, n_lo=1e3, n_hi=1e4))
+    small_rates = {}
+    for batching in (False, True):
+        sv = serve.Server(n_slots=4, hbm_budget=8 << 30, batching=batching)
+        sv.plans = srv.plans
+        sv.run(sjobs[:8])
+        for j in sjobs:
+            j.arrival, j.admitted, j.done, j.slot, j.bypassed = 0.0, float("nan"), float("nan"), -1, 0
+        r = serve.summarize(sv.run(sjobs))
+        small_rates["batched" if batching else "one_by_one"] = {
+            "particles_per_s": r["particles_per_s"], "p50_ms": r["p50_ms"], "evaluations": sv.batches,
+            "requests": r["requests"]}
+        del sv
     del srv
     torch.cuda.empty_cache()
     small = serve.Server(n_slots=4, hbm_budget=8 << 30)
@@ -241,6 +256,8 @@ def serving_leg(n_requests):
         "particles_per_s": loads["0.80"]["particles_per_s"],
         "by_offered_load": loads,
         "hbm_budget_8GiB": budget,
+        "small_requests_saturated": dict(small_rates, workload="256 requests, N log-uniform [1e3, 1e4], "
+                                         "boxes 1^3 or 1x1x2, tol in {1e-4, 1e-6, 1e-8}, all waiting at t = 0"),
     }
 
 
