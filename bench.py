@@ -26,6 +26,7 @@ METRIC = "particles/s full Stokeslet Ewald eval at 1e-6 rel err; P2G GB/s; p50/p
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 FP32_VECTOR_TFLOPS = 157.3
+FP64_MFMA_PEAK_TFLOPS = 78.6  # dense FP64 matrix (v_mfma_f64_16x16x4f64), the same rate as the vector FMA
 # algorithmic cost of one (target, source) pair inside r_c (documented in the design notes):
 # 39 add/mul (FMA = 2) of the G^N f formula + 7 per special function (rsqrt, exp, erfc).
 # Counted per ordered pair, whatever the kernel executes (the symmetric kernel evaluates the
@@ -50,7 +51,8 @@ def stage_roofline(stages, n, ncell, P, real, pairs, alu_peak_tflops):
 
     sort: bytes N (24 + 48 + 64 + 16) + 12 per cell; P2P: 60 flop per pair in r_c; P2G and G2P: 7 flop per
     (particle, stencil point), bytes 64 per record + one pass over the 3-component grid (+ 72 per particle
-    written/gathered by G2P); FFT+CNV+IFFT: five passes, each reading and writing the 3-component grid.
+    written/gathered by G2P; G2P runs on the FP64 matrix cores, priced against their peak);
+    FFT+CNV+IFFT: five passes, each reading and writing the 3-component grid.
     """
     out = {}
 
@@ -63,7 +65,12 @@ def stage_roofline(stages, n, ncell, P, real, pairs, alu_peak_tflops):
         if nbytes is not None:
             e["GBs"] = nbytes / (ms * 1e-3) / 1e9
         e["bound"] = bound
-        e["frac"] = (e["TFLOPs"] / alu_peak_tflops) if bound == "alu" else (e["GBs"] / HBM_PEAK_GBS)
+        if bound == "alu":
+            e["frac"] = e["TFLOPs"] / alu_peak_tflops
+        elif bound == "mfma":  # FP64 matrix instructions in every mode
+            e["frac"] = e["TFLOPs"] / FP64_MFMA_PEAK_TFLOPS
+        else:
+            e["frac"] = e["GBs"] / HBM_PEAK_GBS
         out[name] = e
 
     grid_bytes = 3 * ncell * real
@@ -72,7 +79,7 @@ def stage_roofline(stages, n, ncell, P, real, pairs, alu_peak_tflops):
         put("p2p", stages["p2p"], flops=pairs * P2P_FLOPS_PER_PAIR, bound="alu")
     put("p2g", stages["p2g"], flops=7.0 * n * P**3, nbytes=64 * n + grid_bytes, bound="alu")
     put("fgc", stages["fgc"], nbytes=5 * 2 * grid_bytes)
-    put("g2p", stages["g2p"], flops=7.0 * n * P**3, nbytes=grid_bytes + (64 + 72) * n, bound="alu")
+    put("g2p", stages["g2p"], flops=7.0 * n * P**3, nbytes=grid_bytes + (64 + 72) * n, bound="mfma")
     return out
 
 

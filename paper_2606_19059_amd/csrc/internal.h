@@ -66,6 +66,15 @@ __host__ __device__ inline int cell_key(int cx, int cy, int cz, const Geometry& 
     return (tile << (3 * b)) | (morton2(cx & m, cy & m) << b) | (cz & m);
 }
 
+// LDS hand-off between the lanes of one wavefront (for data private to one wave of a block,
+// which the other waves need not wait for): orders the wave's LDS accesses before and after it
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Block index -> work item such that each XCD (blocks are dealt to the 8 XCDs round
 // robin) processes one contiguous range of items: neighbouring (cell-sorted) items then
 // share that XCD's L2.  A bijection on [0, nb).

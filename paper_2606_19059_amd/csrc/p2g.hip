@@ -32,16 +32,6 @@ constexpr int kPerWave = 32;  // particles staged per wave and round
 constexpr int kChunk = kWaves * kPerWave;
 constexpr int kMaxRuns = 320; // runs per slab (window rows x z-tile segments)
 
-// LDS hand-off between the lanes of one wavefront (the staged particles of a chunk are
-// private to the wave that stages and spreads them, so the waves of a block need not wait
-// for each other there): orders the wave's LDS accesses before and after it
-__device__ inline void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // T: arithmetic and accumulation precision; TG: grid element type (the FP32 bulk mode
 // accumulates in FP64 -- the same VALU rate as FP32 without packed math -- and stores FP32).
 // A block of kWaves waves owns one (patch, x-segment): every wave keeps accumulators for

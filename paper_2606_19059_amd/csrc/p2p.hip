@@ -81,6 +81,17 @@ __device__ inline double uniform_d(double v)
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// minimum over the wave of v in [0, 63], by six ballots (no cross-lane data movement: the
+// shuffle form of this reduction put six dependent LDS round trips into every batch)
+__device__ inline int wave_min_small(int v)
+{
+    int lo = 0;
+#pragma unroll
+    for (int b = 32; b >= 1; b >>= 1)
+        if (__builtin_amdgcn_ballot_w64(v < lo + b) == 0ull) lo += b;
+    return lo;
+}
+
 // number of set bits of m in the lanes below this one
 __device__ inline int lanes_below(unsigned long long m)
 {
@@ -648,7 +659,7 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
         // 3a. rounds in which every lane still takes a pair of its own target (about a third
         //     at uniform density): no queue, no ballot, and the target's position and force
         //     come from registers
-        const int own_all = uniform_i((int)wave_min((double)own_n));
+        const int own_all = wave_min_small(own_n);
         const TF mf0 = (TF)me.f[0], mf1 = (TF)me.f[1], mf2 = (TF)me.f[2];
         for (int r = 0; r < own_all; ++r) {
             const int sl = (__ffs(rm) - 1 + rot) & (kB - 1);

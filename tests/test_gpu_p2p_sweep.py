@@ -110,8 +110,8 @@ def test_p2p_sweep_stresslet_matches_oracle(case):
 
 @pytest.mark.parametrize("case", [1, 3, 5, 8, 10, 11])
 def test_far_field_sweep_matches_oracle(case):
-    """G2P (grouped gathers: 16 targets per wavefront on FP64 grids, 32 on FP32 grids) and
-    P2G on the same sweep, against the spectral oracle's far field."""
+    """G2P (16-target groups contracted on the matrix cores) and P2G on the same sweep, against
+    the spectral oracle's far field."""
     from oracle import spectral as S
 
     E = _E()

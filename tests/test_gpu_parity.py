@@ -354,9 +354,9 @@ def test_largest_grid():
 
 def test_g2p_on_a_large_grid_with_clusters():
     """G2P on a 256^3 grid (three precisions) against the spectral oracle's far field.
-    Particles: a tight cluster, a looser one, one straddling the periodic corner (stencil runs
-    that cross the z boundary take the element-wise loads) and a uniform sprinkle, so the
-    16-target groups span small, medium and large regions."""
+    Particles: a tight cluster, a looser one, one straddling the periodic corner (groups whose
+    box wraps in x, y and z) and a uniform sprinkle, so the 16-target groups span small, medium
+    and large boxes."""
     E = _E()
     box, grid, xi, P = (1.0, 1.0, 1.0), (256, 256, 256), 60.0, 8
     rng = np.random.default_rng(31)
@@ -371,6 +371,49 @@ def test_g2p_on_a_large_grid_with_clusters():
         err = maxrel(host(uf), ref)
         print("256^3 %s tol %g (FP64 grid: %s): far-field max rel err %.2e" % (prec, tol, pl.info["fourier_fp64"], err))
         assert err < bound
+
+
+# G2P groups 16 targets of one tile and contracts their shared box of grid points on the matrix
+# cores; the tile edge B (chosen from n_max per cell: 2, 4, 8 or 16 cells) fixes the number of
+# 16-column blocks, 3 (B + P - 1) / 16 rounded up (1 to 6).  Each case: (box, grid, n_max, n, P,
+# precision, expected B).
+G2P_TILE_CASES = [
+    ((1.0, 1.0, 1.0), (16, 16, 16), 65536, 3000, 4, "fp64", 2),     # 1 column block
+    ((1.0, 1.0, 1.0), (32, 32, 32), 524288, 4000, 10, "fp64", 2),   # 3
+    ((1.0, 1.0, 1.0), (16, 16, 16), 16384, 5000, 6, "fp64", 4),     # 2
+    ((1.0, 1.2, 0.9), (32, 32, 32), 16384, 6000, 16, "fp64", 8),    # 5
+    ((1.0, 1.0, 1.0), (32, 32, 32), 4000, 4000, 16, "fp64", 16),    # 6
+    ((2.0, 1.0, 1.0), (64, 32, 32), 8000, 3000, 12, "fp64", 16),    # 6, non-cubic grid
+    ((1.0, 1.0, 1.0), (32, 32, 32), 16384, 6000, 12, "fp32", 8),    # FP32 grid
+    ((1.0, 1.0, 1.0), (32, 32, 32), 4000, 3000, 14, "fp32", 16),
+]
+
+
+@pytest.mark.parametrize("case", range(len(G2P_TILE_CASES)))
+def test_g2p_every_tile_size(case):
+    """G2P at every tile edge (1 to 6 column blocks), P from 4 to 16, against the spectral
+    oracle's far field.  A quarter of the particles sit within two cells of a periodic face or
+    corner (boxes that wrap), some positions repeat, and the tiles' short chunks leave waves
+    with fewer than 16 targets or none."""
+    E = _E()
+    box, grid, n_max, n, P, prec, B = G2P_TILE_CASES[case]
+    rng = np.random.default_rng(700 + case)
+    L = np.array(box)[:, None]
+    h = L / np.array(grid)[:, None]
+    x = rng.random((3, n)) * L
+    k = n // 4
+    x[:, :k] = np.mod(rng.choice([-1.0, 1.0], (3, k)) * rng.random((3, k)) * 2 * h, L)
+    x[:, k:k + 20] = x[:, k + 20:k + 40]  # repeated positions
+    f = rng.standard_normal((3, n))
+    m = 0.94 * math.sqrt(math.pi * P)
+    tol = 1e-11 if prec == "fp64" else 1e-5
+    pl = E.Plan(box, tol, xi=8.0, r_c=0.2, grid=grid, P=P, window_shape=m, n_max=n_max, precision=prec)
+    assert pl.info["tile"] == B
+    _, uf = pl.eval_parts(dev(x), dev(f))
+    err = maxrel(host(uf), S.far_field(x, f, box, grid, 8.0, P, m))
+    bound = 1e-11 if prec == "fp64" else 2e-5
+    print("G2P tile %d, P %d, %s %s: far-field max rel err %.2e" % (B, P, prec, grid, err))
+    assert err < bound
 
 
 # ---------------------------------------------------------------- failure handling
