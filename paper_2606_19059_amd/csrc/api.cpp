@@ -196,13 +196,13 @@ constexpr double kFourierFp32MinTol = 1e-6;
 struct CostModel {
     double pair, p2p0;          // ms per 1e9 evaluated pairs (each unordered pair once), fixed
     double p2g, p2g_cell, p2g0; // ms per 1e9 N P^3 at full occupancy, per 1e6 cells, fixed
-    double g2p, g2p_big, g2p_cell, g2p0;
+    double g2p, g2p_group, g2p_cell, g2p0;  // ms per 1e9 matrix steps, per 1e6 groups, per 1e6 cells, fixed
     double fft_cell, fft0;
     double sort, sort_cell, sort0;
 };
-constexpr CostModel kCost64 = {6.437, 0.199, 0.108, 0.169, 0.072, 0.964, 0.053, 0.117, 0.062, 0.086, 0.028,
+constexpr CostModel kCost64 = {6.437, 0.199, 0.108, 0.169, 0.072, 43.585, 2.914, 0.0039, 0.0, 0.086, 0.028,
                                0.216, 0.008, 0.044};
-constexpr CostModel kCost32 = {5.462, 0.245, 0.146, 0.171, 0.059, 0.561, 0.068, 0.061, 0.051, 0.055, 0.037,
+constexpr CostModel kCost32 = {5.462, 0.245, 0.146, 0.171, 0.059, 53.008, 2.957, 0.0, 0.0041, 0.055, 0.037,
                                0.223, 0.006, 0.044};
 constexpr double kWaveSlots = 2048.0;  // concurrent P2P waves at which the chip is full
 
@@ -228,12 +228,23 @@ double model_ms(int mode, bool grid64, double n, const double box[3], const int 
     const double split = (tiles + std::ceil(n / 64.0) < 40000.0) ? 3.0 : 1.0;
     const double waves = (n / 64.0 + 0.5 * tiles) * split;
     const double np3 = n * P * P * P;
+    // G2P: groups of 16 targets of one tile; each runs ceil(U^2 / 4) x NB matrix steps, U = P - 1 +
+    // the x (and y) spread of its targets (a 16-target run of a tile's Morton columns: about
+    // 4 B / sqrt(particles per tile) cells, at most B), NB = ceil(3 (B + P - 1) / 16); four waves
+    // per 64-target chunk fill the chip from 4096 waves on
+    const double per_tile = std::max(n / tiles, 1e-9);
+    const double spread = std::min((double)B, std::max(1.0, 4.0 * B / std::sqrt(per_tile)));
+    const double U = P - 1 + spread;
+    const double NB = std::ceil(3.0 * (B + P - 1) / 16.0);
+    const double groups = tiles * std::ceil(per_tile / 16.0);
+    const double g2p_occ = std::min(1.0, 4.0 * (n / 64.0 + tiles) / 4096.0);
     double st[5];
     st[0] = c.sort * n * 1e-6 + c.sort_cell * cells * 1e-6 + c.sort0;
     st[1] = c.pair * pairs * 1e-9 / std::min(1.0, waves / kWaveSlots) + c.p2p0;
     st[2] = c.p2g * np3 * 1e-9 / std::min(1.0, p2g_blocks(M, P) / 1024.0) + c.p2g_cell * cells * 1e-6 + c.p2g0;
     st[3] = cf.fft_cell * cells * 1e-6 + cf.fft0;
-    st[4] = c.g2p * np3 * 1e-9 + c.g2p_big * np3 * 1e-9 * cells * 1e-7 + c.g2p_cell * cells * 1e-6 + c.g2p0;
+    st[4] = (c.g2p * groups * std::ceil(U * U / 4.0) * NB * 1e-9 + c.g2p_group * groups * 1e-6) / g2p_occ +
+            c.g2p_cell * cells * 1e-6 + c.g2p0;
     double t = 0;
     for (int k = 0; k < 5; ++k) {
         if (stage) stage[k] = st[k];
