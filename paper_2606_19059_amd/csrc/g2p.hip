@@ -104,8 +104,11 @@ constexpr int kMWaves = 4;  // waves per block: one 64-target chunk of a tile
 // column blocks of a plan: 3 (B + P - 1) columns
 constexpr int g2p_mfma_blocks(int B, int P) { return (3 * (B + P - 1) + 15) / 16; }
 
+// Up to five column blocks the kernel is bounded to 96 VGPRs (five waves per SIMD instead of
+// four): the loads of a step wait on L2 most of the time, and the fifth wave hides more of it
+// (c3 5.73 -> 5.47 ms, H 0.79 -> 0.77 ms, c2 unchanged); six blocks would spill under that bound.
 template <typename T, typename TG, int P, int NB>
-__global__ __launch_bounds__(kMWaves * 64) void k_g2p_mfma(const typename RecView<T>::Rec* __restrict__ rec,
+__global__ __launch_bounds__(kMWaves * 64) __attribute__((amdgpu_waves_per_eu(NB <= 5 ? 5 : 4))) void k_g2p_mfma(const typename RecView<T>::Rec* __restrict__ rec,
                                                            const int* __restrict__ start,
                                                            const int* __restrict__ chunk_off,
                                                            const TG* __restrict__ grid, Geometry g, WinArgs<T> wa,
