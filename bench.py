@@ -420,8 +420,10 @@ def main():
     p2p_s = stages["p2p"] * 1e-3
     peak = FP64_VECTOR_TFLOPS if precision == "fp64" else FP32_VECTOR_TFLOPS
     achieved = (pairs * P2P_FLOPS_PER_PAIR / p2p_s / 1e12) if pairs else None
-    kernel = ("k_p2p_sym<double, %s, false>" % ("true" if wl.tol >= 1e-10 else "false")) if precision == "fp64" \
-        else "k_p2p_sym<float, false, false>"
+    # the symmetric kernel's instance: FP64 at the pair formula's accuracy level for this tol
+    # (2: tol >= 1e-8, 1: tol >= 1e-10, 0: full), or the FP32 formula
+    level = 2 if wl.tol >= 1e-8 else 1 if wl.tol >= 1e-10 else 0
+    kernel = ("k_p2p_sym<double, %d, false>" % level) if precision == "fp64" else "k_p2p_sym<float, 0, false>"
     roofline = {
         "kernel": kernel,
         "bound": "alu",

@@ -222,10 +222,11 @@ double model_ms(int mode, bool grid64, double n, const double box[3], const int 
     const double cells = (double)M[0] * M[1] * M[2];
     const double pairs = 0.5 * n * n / V * (4.0 / 3.0) * M_PI * rc * rc * rc;
     // P2P waves: one per 64-target chunk (about n/64 + tiles/2), three per chunk when the
-    // launch has few chunks (the rule of launch_p2p in p2p.hip, on its grid of tiles + n/64
-    // chunks: fewer than 40000)
+    // launch has few chunks, four when it has very few (the rule of launch_p2p in p2p.hip, on
+    // its grid of tiles + n/64 chunks: fewer than 40000, fewer than 2048)
     const double tiles = cells / ((double)B * B * B);
-    const double split = (tiles + std::ceil(n / 64.0) < 40000.0) ? 3.0 : 1.0;
+    const double grid_waves = tiles + std::ceil(n / 64.0);
+    const double split = grid_waves < 2048.0 ? 4.0 : grid_waves < 40000.0 ? 3.0 : 1.0;
     const double waves = (n / 64.0 + 0.5 * tiles) * split;
     const double np3 = n * P * P * P;
     // G2P: groups of 16 targets of one tile; each runs ceil(U^2 / 4) x NB matrix steps, U = P - 1 +

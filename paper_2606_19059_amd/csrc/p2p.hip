@@ -30,11 +30,16 @@ namespace ewald {
 
 namespace {
 
-// Reduced-cost FP64 pair formula for plans with tol >= 1e-10: degree-12 screening
-// polynomial (|dC| < 4e-12), e^{-y} from a Cody-Waite reduction and a degree-9 Taylor
-// polynomial (relative error < 7e-12 for |f| <= ln2/2; no range checks: 0 <= y < 42.3
-// on the P2P range), and one Newton step on the hardware reciprocal.
-constexpr int kExpDeg = 9;
+// Accuracy levels of the FP64 pair formula (template argument Lv), chosen from the plan's tol so
+// that the formula's own error stays 30-40 times below it:
+//   0 (tol < 1e-10): degree-16 screening polynomial (|dC| < 5e-15), library exponential, two
+//     Newton steps on the hardware reciprocal, third-order rsqrt correction;
+//   1 (1e-10 <= tol < 1e-8): degree 12 (|dC| < 4e-12), e^{-y} from a Cody-Waite reduction and a
+//     degree-8 Chebyshev polynomial of e^f on |f| <= ln2/2 (relative error 1.1e-12; no range
+//     checks: 0 <= y < 42.3 on the P2P range), one Newton step on rcp and on rsqrt;
+//   2 (tol >= 1e-8): degree 10 (|dC| < 3e-10) and a degree-7 polynomial of e^f (5.6e-11), else
+//     as level 1: near-field error about 2.5e-10 of the field's max (a CPU model of c2's and of a
+//     coarse plan's geometry), four FMAs fewer per pair than level 1.
 constexpr double kLog2e = 1.4426950408889634074;
 constexpr double kLn2Hi = 6.93147180369123816490e-01;  // ln 2 split (Cody and Waite): n ln2_hi exact
 constexpr double kLn2Lo = 1.90821492927058770002e-10;
@@ -43,12 +48,12 @@ struct PairArgs {
     double xi, xi2, rc2;
     double four_xi_over_sqrtpi;
     double xi2_log2e;
-    // screening polynomial, passed by value so that the coefficients sit in scalar
-    // registers (an FMA then takes them as an operand, no per-pair register copies)
-    double c64[kScreenDeg64 + 1];
-    double c64s[kScreenDeg64s + 1];
+    // polynomials of the launched kernel's level (screening cs, exponential ce) or of the FP32
+    // formula (c32), passed by value so that the coefficients sit in scalar registers (an FMA
+    // then takes them as an operand, no per-pair register copies)
+    double cs[kScreenDeg64 + 1];
+    double ce[kExpDeg1 + 1];
     float c32[kScreenDeg32 + 1];
-    double ec[kExpDeg + 1];  // 1/k!, Taylor coefficients of e^f
     double six_xi_over_sqrtpi, four_xi3_over_sqrtpi;  // stresslet screening
 };
 
@@ -100,16 +105,16 @@ __device__ inline int lanes_below(unsigned long long m)
 }
 
 // erfcx(x) + 2x/sqrt(pi) for 0 <= x <= kScreenXmax (polynomial of screening.h)
-template <bool Fast>
+template <int Lv>
 __device__ inline double screen_q64(double x, const PairArgs& a)
 {
     const double d = x + kScreenK;
     double r = __builtin_amdgcn_rcp(d);
     r = fma(fma(-d, r, 1.0), r, r);
-    if (!Fast) r = fma(fma(-d, r, 1.0), r, r);
+    if (Lv == 0) r = fma(fma(-d, r, 1.0), r, r);
     const double u = fma((x - kScreenK) * r, kScreenA, kScreenB);
-    constexpr int deg = Fast ? kScreenDeg64s : kScreenDeg64;
-    const double* c = Fast ? a.c64s : a.c64;
+    constexpr int deg = Lv == 0 ? kScreenDeg64 : Lv == 1 ? kScreenDeg64s : kScreenDeg64f;
+    const double* c = a.cs;
     double q = c[deg];
 #pragma unroll
     for (int k = deg - 1; k >= 0; --k) q = fma(q, u, c[k]);
@@ -117,38 +122,41 @@ __device__ inline double screen_q64(double x, const PairArgs& a)
 }
 
 // e^{-y} for 0 <= y < 42.3: y = -n ln2 - f with n = rint(-y log2 e), |f| <= ln2 / 2
+template <int Lv>
 __device__ inline double exp_neg_fast(double y, const PairArgs& a)
 {
     const double n = rint(-y * kLog2e);
     const double f = fma(n, -kLn2Lo, fma(n, -kLn2Hi, -y));
-    double p = a.ec[kExpDeg];
+    constexpr int deg = Lv == 1 ? kExpDeg1 : kExpDeg2;
+    const double* c = a.ce;
+    double p = c[deg];
 #pragma unroll
-    for (int k = kExpDeg - 1; k >= 0; --k) p = fma(p, f, a.ec[k]);
+    for (int k = deg - 1; k >= 0; --k) p = fma(p, f, c[k]);
     return ldexp(p, (int)n);
 }
 
 // 1/sqrt(r2) for finite r2 > 0: hardware estimate y (error bound 2^29 ulp, ~2^-23
 // relative), then with e = 1 - r2 y^2 one third-order correction y (1 + e/2 + 3e^2/8) (full
-// FP64), or for Fast one Newton step y (1 + e/2) (relative error ~ 3e^2/8, below 1e-13).
-// No special values.
-template <bool Fast>
+// FP64), or for levels 1 and 2 one Newton step y (1 + e/2) (relative error ~ 3e^2/8, below
+// 1e-13).  No special values.
+template <int Lv>
 __device__ inline double rsqrt_pos(double r2)
 {
     const double y = __builtin_amdgcn_rsq(r2);
     const double e = fma(-r2 * y, y, 1.0);
-    if (Fast) return fma(y * e, 0.5, y);
+    if (Lv > 0) return fma(y * e, 0.5, y);
     return fma(y * e, fma(0.375, e, 0.5), y);
 }
 
 // Coefficients of G^N(r) f = a1 f + b (r.f) r for 0 < r^2 < r_c^2 (FP64):
 // a1 = C/r - (4 xi/sqrt(pi)) e, b = C/r^3
-template <bool Fast>
+template <int Lv>
 __device__ inline void coef64(double r2, const PairArgs& a, double& a1, double& b)
 {
-    const double rinv = rsqrt_pos<Fast>(r2);
+    const double rinv = rsqrt_pos<Lv>(r2);
     const double x = a.xi * r2 * rinv;
-    const double e = Fast ? exp_neg_fast(a.xi2 * r2, a) : exp(-a.xi2 * r2);
-    const double Cr = e * screen_q64<Fast>(x, a) * rinv;
+    const double e = Lv > 0 ? exp_neg_fast<Lv>(a.xi2 * r2, a) : exp(-a.xi2 * r2);
+    const double Cr = e * screen_q64<Lv>(x, a) * rinv;
     a1 = fma(-a.four_xi_over_sqrtpi, e, Cr);
     b = Cr * (rinv * rinv);
 }
@@ -181,19 +189,19 @@ __device__ inline void coef32(double r2d, const PairArgs& a, float& a1, float& b
     b = Cr * (rinv * rinv);
 }
 
-// Pair coefficients in the formula precision TF (double: FP64 path, Fast for tol >= 1e-10;
-// float: FP32 bulk).
-template <typename TF, bool Fast>
+// Pair coefficients in the formula precision TF (double: FP64 path at accuracy level Lv;
+// float: FP32 bulk, Lv unused).
+template <typename TF, int Lv>
 struct Coef;
-template <bool Fast>
-struct Coef<double, Fast> {
+template <int Lv>
+struct Coef<double, Lv> {
     __device__ static inline void eval(double r2, const PairArgs& a, double& a1, double& b)
     {
-        coef64<Fast>(r2, a, a1, b);
+        coef64<Lv>(r2, a, a1, b);
     }
 };
-template <bool Fast>
-struct Coef<float, Fast> {
+template <int Lv>
+struct Coef<float, Lv> {
     __device__ static inline void eval(double r2, const PairArgs& a, float& a1, float& b) { coef32(r2, a, a1, b); }
 };
 
@@ -204,14 +212,14 @@ struct Coef<float, Fast> {
 //   beta = 4 xi^3 e^{-xi^2 r^2} / sqrt(pi).
 // Both follow from the same exponential and screening polynomial as G^N:
 // erfc(x) = C - (2x/sqrt(pi)) e^{-x^2}.
-template <bool Fast>
+template <int Lv>
 __device__ inline void coef64_st(double r2, const PairArgs& a, double& a1, double& b, double& al, double& be)
 {
     const double rinv = rsqrt(r2);
     const double r = r2 * rinv;
     const double x = a.xi * r;
-    const double e = Fast ? exp_neg_fast(a.xi2 * r2, a) : exp(-a.xi2 * r2);
-    const double C = e * screen_q64<Fast>(x, a);
+    const double e = Lv > 0 ? exp_neg_fast<Lv>(a.xi2 * r2, a) : exp(-a.xi2 * r2);
+    const double C = e * screen_q64<Lv>(x, a);
     const double rinv2 = rinv * rinv, rinv3 = rinv2 * rinv;
     a1 = fma(C, rinv, -a.four_xi_over_sqrtpi * e);
     b = C * rinv3;
@@ -239,17 +247,17 @@ __device__ inline void coef32_st(double r2d, const PairArgs& a, float& a1, float
     be = (float)a.four_xi3_over_sqrtpi * e;
 }
 
-template <typename TF, bool Fast>
+template <typename TF, int Lv>
 struct CoefSt;
-template <bool Fast>
-struct CoefSt<double, Fast> {
+template <int Lv>
+struct CoefSt<double, Lv> {
     __device__ static inline void eval(double r2, const PairArgs& a, double& a1, double& b, double& al, double& be)
     {
-        coef64_st<Fast>(r2, a, a1, b, al, be);
+        coef64_st<Lv>(r2, a, a1, b, al, be);
     }
 };
-template <bool Fast>
-struct CoefSt<float, Fast> {
+template <int Lv>
+struct CoefSt<float, Lv> {
     __device__ static inline void eval(double r2, const PairArgs& a, float& a1, float& b, float& al, float& be)
     {
         coef32_st(r2, a, a1, b, al, be);
@@ -289,7 +297,7 @@ constexpr int kTest = 32;    // sources tested per round (queue <= kTest * 64 pa
 // Count: no pair formula; the wave only counts its accepted (target, source) pairs and adds
 // the count to *pair_count (one integer atomic per wave): the exact number of ordered pairs
 // the near-field sum runs over, for measurement.
-template <typename TF, typename TA, bool Fast, bool Count = false>
+template <typename TF, typename TA, int Lv, bool Count = false>
 __global__ __launch_bounds__(64) void k_p2p(int n, const Rec64* __restrict__ rec,
                                             const int* __restrict__ start,
                                             const int* __restrict__ chunk_off, Geometry g,
@@ -370,7 +378,7 @@ __global__ __launch_bounds__(64) void k_p2p(int n, const Rec64* __restrict__ rec
                 const double rz = tgt[2][tt] - ring[2][slot];
                 const double r2 = rx * rx + ry * ry + rz * rz;
                 TF a1, b, c0, c1, c2;
-                Coef<TF, Fast>::eval(r2, a, a1, b);
+                Coef<TF, Lv>::eval(r2, a, a1, b);
                 apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, ringf[0][slot], ringf[1][slot], ringf[2][slot], c0, c1, c2);
                 atomicAdd(&acc[0][tt], (TA)c0);
                 atomicAdd(&acc[1][tt], (TA)c1);
@@ -512,7 +520,7 @@ __global__ void k_zero_f64(double* __restrict__ p, int64_t count)
 
 // ST: stresslet sources too (srec: sorted symmetric tensors, 6 per particle); T^N is odd,
 // so the source side of a pair takes -T^N(r) S_target.
-template <typename TF, bool Fast, bool ST>
+template <typename TF, int Lv, bool ST>
 __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__ rec,
                                                 const double* __restrict__ srec,
                                                 const int* __restrict__ start,
@@ -697,7 +705,7 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
             TF a1, b;
             if constexpr (ST) {
                 TF al, be;
-                CoefSt<TF, Fast>::eval(r2, a, a1, b, al, be);
+                CoefSt<TF, Lv>::eval(r2, a, a1, b, al, be);
                 apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, ringf[0][slot], ringf[1][slot], ringf[2][slot], c0, c1, c2);
                 apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, tf0, tf1, tf2, d0, d1, d2);
                 TF ss[6], st[6];
@@ -709,7 +717,7 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
                 apply_st<TF>(al, be, (TF)rx, (TF)ry, (TF)rz, ss, c0, c1, c2);
                 apply_st<TF>(al, be, (TF)rx, (TF)ry, (TF)rz, st, d0, d1, d2);
             } else {
-                Coef<TF, Fast>::eval(r2, a, a1, b);
+                Coef<TF, Lv>::eval(r2, a, a1, b);
                 apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, ringf[0][slot], ringf[1][slot], ringf[2][slot], c0, c1, c2);
                 apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, tf0, tf1, tf2, d0, d1, d2);
             }
@@ -887,7 +895,7 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
 
 namespace {
 
-PairArgs pair_args(const Plan& pl)
+PairArgs pair_args(const Plan& pl, int lv)
 {
     PairArgs a;
     a.xi = pl.xi;
@@ -897,14 +905,13 @@ PairArgs pair_args(const Plan& pl)
     a.xi2_log2e = a.xi2 * 1.4426950408889634;
     a.six_xi_over_sqrtpi = 6.0 * pl.xi / sqrt(M_PI);
     a.four_xi3_over_sqrtpi = 4.0 * pl.xi * pl.xi * pl.xi / sqrt(M_PI);
-    for (int k = 0; k <= kScreenDeg64; ++k) a.c64[k] = kScreenC64[k];
-    for (int k = 0; k <= kScreenDeg64s; ++k) a.c64s[k] = kScreenC64s[k];
+    const double* cs = lv == 2 ? kScreenC64f : lv == 1 ? kScreenC64s : kScreenC64;
+    const int ds = lv == 2 ? kScreenDeg64f : lv == 1 ? kScreenDeg64s : kScreenDeg64;
+    for (int k = 0; k <= kScreenDeg64; ++k) a.cs[k] = k <= ds ? cs[k] : 0.0;
+    const double* ce = lv == 2 ? kExpC2 : kExpC1;
+    const int de = lv == 2 ? kExpDeg2 : kExpDeg1;
+    for (int k = 0; k <= kExpDeg1; ++k) a.ce[k] = k <= de ? ce[k] : 0.0;
     for (int k = 0; k <= kScreenDeg32; ++k) a.c32[k] = (float)kScreenC32[k];
-    double fact = 1.0;
-    for (int k = 0; k <= kExpDeg; ++k) {
-        a.ec[k] = 1.0 / fact;
-        fact *= (double)(k + 1);
-    }
     return a;
 }
 
@@ -917,71 +924,79 @@ hipError_t launch_count_pairs(const Plan& pl, const Work& w, int n, unsigned lon
 {
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, count);
     if (n > 0) {
-        const PairArgs a = pair_args(pl);
+        const PairArgs a = pair_args(pl, 0);
         Geometry g = pl.g;
         g.nsys = nsys;
         const int64_t waves = (int64_t)g.ntiles * nsys + (n + kWave - 1) / kWave;
-        hipLaunchKernelGGL((k_p2p<double, double, false, true>), dim3((unsigned)waves), dim3(kWave), 0, s, n,
+        hipLaunchKernelGGL((k_p2p<double, double, 0, true>), dim3((unsigned)waves), dim3(kWave), 0, s, n,
                            (const Rec64*)w.rec, w.start, w.chunk_off, g, a, nullptr, count);
     }
     return hipGetLastError();
 }
 
+// the FP64 pair formula's accuracy level for a plan's tolerance (see PairArgs)
+static int pair_level(double tol) { return tol >= 1e-8 ? 2 : tol >= 1e-10 ? 1 : 0; }
+
+template <typename TF, int Lv>
+void launch_p2p_det(const Plan& pl, const Work& w, int n, hipStream_t s, const Geometry& g, const PairArgs& a,
+                    dim3 grid)
+{
+    hipLaunchKernelGGL((k_p2p<TF, double, Lv>), grid, dim3(kWave), 0, s, n, (const Rec64*)w.rec, w.start,
+                       w.chunk_off, g, a, w.u_near);
+}
+
+template <typename TF, int Lv, bool ST>
+void launch_p2p_sym(const Work& w, int n, hipStream_t s, const Geometry& g, const PairArgs& a, dim3 grid, int split)
+{
+    hipLaunchKernelGGL((k_p2p_sym<TF, Lv, ST>), grid, dim3(kWave), 0, s, n, (const Rec64*)w.rec, w.srec, w.start,
+                       w.chunk_off, g, a, w.u_near, split);
+}
+
 hipError_t launch_p2p(const Plan& pl, const Work& w, int n, hipStream_t s, bool st, int nsys)
 {
     if (n <= 0) return hipSuccess;
-    const PairArgs a = pair_args(pl);
+    const bool f64 = pl.mode == EWALD_FP64;
+    const int lv = f64 ? pair_level(pl.p.tol) : -1;  // -1: the FP32 formula
+    const PairArgs a = pair_args(pl, lv < 0 ? 0 : lv);
     Geometry g = pl.g;
     g.nsys = nsys;
-    const bool fast = pl.p.tol >= 1e-10;
     const int64_t waves = (int64_t)g.ntiles * nsys + (n + kWave - 1) / kWave;
-    const dim3 grid((unsigned)waves), block(kWave);
-    const Rec64* rec = (const Rec64*)w.rec;
-    const bool f64 = pl.mode == EWALD_FP64;
+    const dim3 grid((unsigned)waves);
     if (pl.deterministic && !st) {
         // FP32 bulk accumulates in FP64 as well: LDS atomic adds of FP64 are fast on
         // gfx950, those of FP32 are not (measured: 3x slower kernel)
-        if (f64 && fast)
-            hipLaunchKernelGGL((k_p2p<double, double, true>), grid, block, 0, s, n, rec, w.start, w.chunk_off,
-                               g, a, w.u_near);
-        else if (f64)
-            hipLaunchKernelGGL((k_p2p<double, double, false>), grid, block, 0, s, n, rec, w.start, w.chunk_off,
-                               g, a, w.u_near);
-        else
-            hipLaunchKernelGGL((k_p2p<float, double, false>), grid, block, 0, s, n, rec, w.start, w.chunk_off,
-                               g, a, w.u_near);
+        switch (lv) {
+        case 0: launch_p2p_det<double, 0>(pl, w, n, s, g, a, grid); break;
+        case 1: launch_p2p_det<double, 1>(pl, w, n, s, g, a, grid); break;
+        case 2: launch_p2p_det<double, 2>(pl, w, n, s, g, a, grid); break;
+        default: launch_p2p_det<float, 0>(pl, w, n, s, g, a, grid); break;
+        }
         return hipGetLastError();
     }
     // Symmetric kernel: with few chunks per wave slot of the chip (c2: 15.6k chunks, about 4 per
     // slot), three waves per chunk shorten the waves and so the launch's tail (measured at c2:
-    // 25.5 -> 24.2 ms; two: 24.5, four: 25.3); with many (c3: 156k) one (two and four were
-    // slower there).
-    const int kSplit = waves < 40000 ? 3 : 1;
+    // 25.5 -> 24.2 ms; two: 24.5, four: 25.3; again with the matrix-core cutoff test: three 21.4,
+    // two 21.6, four 22.4 ms); with many (c3: 156k) one (two and four were slower there); with
+    // fewer chunks than wave slots, four (c1, N = 1e3: 0.097 -> 0.071 ms).
+    const int kSplit = waves < 2048 ? 4 : waves < 40000 ? 3 : 1;
     const dim3 sgrid((unsigned)(waves * kSplit));
     const int64_t cnt = 3 * (int64_t)n;
     hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, w.u_near, cnt);
-    const double* sr = w.srec;
     if (st) {
-        if (f64 && fast)
-            hipLaunchKernelGGL((k_p2p_sym<double, true, true>), sgrid, block, 0, s, n, rec, sr, w.start, w.chunk_off,
-                               g, a, w.u_near, kSplit);
-        else if (f64)
-            hipLaunchKernelGGL((k_p2p_sym<double, false, true>), sgrid, block, 0, s, n, rec, sr, w.start,
-                               w.chunk_off, g, a, w.u_near, kSplit);
-        else
-            hipLaunchKernelGGL((k_p2p_sym<float, false, true>), sgrid, block, 0, s, n, rec, sr, w.start,
-                               w.chunk_off, g, a, w.u_near, kSplit);
+        switch (lv) {
+        case 0: launch_p2p_sym<double, 0, true>(w, n, s, g, a, sgrid, kSplit); break;
+        case 1: launch_p2p_sym<double, 1, true>(w, n, s, g, a, sgrid, kSplit); break;
+        case 2: launch_p2p_sym<double, 2, true>(w, n, s, g, a, sgrid, kSplit); break;
+        default: launch_p2p_sym<float, 0, true>(w, n, s, g, a, sgrid, kSplit); break;
+        }
         return hipGetLastError();
     }
-    if (f64 && fast)
-        hipLaunchKernelGGL((k_p2p_sym<double, true, false>), sgrid, block, 0, s, n, rec, sr, w.start, w.chunk_off,
-                           g, a, w.u_near, kSplit);
-    else if (f64)
-        hipLaunchKernelGGL((k_p2p_sym<double, false, false>), sgrid, block, 0, s, n, rec, sr, w.start,
-                           w.chunk_off, g, a, w.u_near, kSplit);
-    else
-        hipLaunchKernelGGL((k_p2p_sym<float, false, false>), sgrid, block, 0, s, n, rec, sr, w.start,
-                           w.chunk_off, g, a, w.u_near, kSplit);
+    switch (lv) {
+    case 0: launch_p2p_sym<double, 0, false>(w, n, s, g, a, sgrid, kSplit); break;
+    case 1: launch_p2p_sym<double, 1, false>(w, n, s, g, a, sgrid, kSplit); break;
+    case 2: launch_p2p_sym<double, 2, false>(w, n, s, g, a, sgrid, kSplit); break;
+    default: launch_p2p_sym<float, 0, false>(w, n, s, g, a, sgrid, kSplit); break;
+    }
     return hipGetLastError();
 }
 
