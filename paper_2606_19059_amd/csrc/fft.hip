@@ -198,8 +198,11 @@ __global__ __launch_bounds__(256) void k_fft_y(T* __restrict__ grid, int64_t nce
     C2<T>* b = a + (size_t)M2 * ncols;
     C2<T>* data = reinterpret_cast<C2<T>*>(grid + blockIdx.y * ncells);
     const int tiles_per_x = H / ncols;
-    const int x = blockIdx.x / tiles_per_x;
-    const int kz0 = (blockIdx.x - x * tiles_per_x) * ncols;
+    // blocks of consecutive z-runs share cache lines: each XCD takes a contiguous range of blocks
+    // (blocks are dealt to the 8 XCDs round robin), so that a line is fetched into one L2
+    const int bx = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int x = bx / tiles_per_x;
+    const int kz0 = (bx - x * tiles_per_x) * ncols;
     const int64_t base = (int64_t)x * M2 * H + kz0;
     const int tot = M2 * ncols;
     for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
@@ -236,8 +239,11 @@ __global__ __launch_bounds__(256) void k_fft_x_cnv(T* __restrict__ grid, int64_t
     C2<T>* b = a + (size_t)3 * per;
     grid += (int64_t)blockIdx.y * 3 * ncells;  // system blockIdx.y of a batch
     const int tiles_per_y = H / ncols;
-    const int ky = blockIdx.x / tiles_per_y;
-    const int kz0 = (blockIdx.x - ky * tiles_per_y) * ncols;
+    // runs of ncols z-elements (2 complex at 128^3 FP64): the blocks of one cache line go to one
+    // XCD (see k_fft_y)
+    const int bx = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int ky = bx / tiles_per_y;
+    const int kz0 = (bx - ky * tiles_per_y) * ncols;
     const int64_t rowstride = (int64_t)M2 * H;  // complex elements between consecutive x
     const int tot = 3 * per;
     for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
@@ -300,8 +306,11 @@ __global__ __launch_bounds__(256) void k_cnv_st_x(T* __restrict__ grid, int64_t 
     C2<T>* a = reinterpret_cast<C2<T>*>(smem_raw);
     C2<T>* b = a + (size_t)3 * per;
     const int tiles_per_y = H / ncols;
-    const int ky = blockIdx.x / tiles_per_y;
-    const int kz0 = (blockIdx.x - ky * tiles_per_y) * ncols;
+    // runs of ncols z-elements (2 complex at 128^3 FP64): the blocks of one cache line go to one
+    // XCD (see k_fft_y)
+    const int bx = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int ky = bx / tiles_per_y;
+    const int kz0 = (bx - ky * tiles_per_y) * ncols;
     const int64_t rowstride = (int64_t)M2 * H;
     const int kys = (ky < M2 / 2) ? ky : ky - M2;
     const double k1 = ca.twopi_over_L[1] * kys;
