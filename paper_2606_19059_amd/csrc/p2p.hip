@@ -34,25 +34,30 @@ namespace {
 // that the formula's own error stays 30-40 times below it:
 //   0 (tol < 1e-10): degree-16 screening polynomial (|dC| < 5e-15), library exponential, two
 //     Newton steps on the hardware reciprocal, third-order rsqrt correction;
-//   1 (1e-10 <= tol < 1e-8): degree 12 (|dC| < 4e-12), e^{-y} from a Cody-Waite reduction and a
-//     degree-8 Chebyshev polynomial of e^f on |f| <= ln2/2 (relative error 1.1e-12; no range
-//     checks: 0 <= y < 42.3 on the P2P range), one Newton step on rcp and on rsqrt;
-//   2 (tol >= 1e-8): degree 10 (|dC| < 3e-10) and a degree-7 polynomial of e^f (5.6e-11), else
+//   1 (1e-10 <= tol < 1e-8): degree 12 (|dC| < 4e-12), e^{-y} = 2^z (z = -y log2 e) as 2^n times a
+//     degree-8 Chebyshev polynomial of 2^s, z = n + s, n = rint(z) (relative error 1.1e-12; no
+//     range checks: -61 < z <= 0 on the P2P range), one Newton step on rcp and on rsqrt;
+//   2 (tol >= 1e-8): degree 10 (|dC| < 3e-10) and a degree-7 polynomial of 2^s (5.6e-11), else
 //     as level 1: near-field error about 2.5e-10 of the field's max (a CPU model of c2's and of a
-//     coarse plan's geometry), four FMAs fewer per pair than level 1.
+//     coarse plan's geometry).
+// Both polynomials are stored divided by their leading coefficients (screening.h), so that Horner
+// starts with an addition (an FMA cannot take two scalar-register coefficients).  The FP64 pair
+// formula therefore returns its coefficients divided by post = lead_screen x lead_exp (lead_exp = 1
+// at level 0); the kernels multiply each target's and source's sum by post once, at the end.
 constexpr double kLog2e = 1.4426950408889634074;
-constexpr double kLn2Hi = 6.93147180369123816490e-01;  // ln 2 split (Cody and Waite): n ln2_hi exact
-constexpr double kLn2Lo = 1.90821492927058770002e-10;
 
 struct PairArgs {
     double xi, xi2, rc2;
     double four_xi_over_sqrtpi;
     double xi2_log2e;
-    // polynomials of the launched kernel's level (screening cs, exponential ce) or of the FP32
-    // formula (c32), passed by value so that the coefficients sit in scalar registers (an FMA
-    // then takes them as an operand, no per-pair register copies)
-    double cs[kScreenDeg64 + 1];
-    double ce[kExpDeg1 + 1];
+    // FP64 formula of the launched level: z = zc r^2 (zc = -xi^2 log2 e); monic screening (ms,
+    // x coefficient g = (2/sqrt(pi))/lead_s) and exponential (me) polynomials; a1 / post =
+    // C'/r - h e' with h = (4 xi/sqrt(pi))/lead_s
+    double zc, g, h, post, lead_s, lead_e;
+    // polynomials passed by value, so that the coefficients sit in scalar registers (an FMA then
+    // takes them as an operand, no per-pair register copies); c32: the FP32 formula's
+    double ms[kScreenDeg64];
+    double me[kExpDeg1];
     float c32[kScreenDeg32 + 1];
     double six_xi_over_sqrtpi, four_xi3_over_sqrtpi;  // stresslet screening
 };
@@ -104,7 +109,8 @@ __device__ inline int lanes_below(unsigned long long m)
                                           __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
-// erfcx(x) + 2x/sqrt(pi) for 0 <= x <= kScreenXmax (polynomial of screening.h)
+// (erfcx(x) + 2x/sqrt(pi)) / lead_s for 0 <= x <= kScreenXmax: the monic polynomial of screening.h
+// in t = (x - K)/(x + K) = 1 - 2K/(x + K), plus g x
 template <int Lv>
 __device__ inline double screen_q64(double x, const PairArgs& a)
 {
@@ -112,26 +118,27 @@ __device__ inline double screen_q64(double x, const PairArgs& a)
     double r = __builtin_amdgcn_rcp(d);
     r = fma(fma(-d, r, 1.0), r, r);
     if (Lv == 0) r = fma(fma(-d, r, 1.0), r, r);
-    const double u = fma((x - kScreenK) * r, kScreenA, kScreenB);
+    const double t = fma(-2.0 * kScreenK, r, 1.0);
     constexpr int deg = Lv == 0 ? kScreenDeg64 : Lv == 1 ? kScreenDeg64s : kScreenDeg64f;
-    const double* c = a.cs;
-    double q = c[deg];
+    const double* m = a.ms;
+    double q = t + m[deg - 1];
 #pragma unroll
-    for (int k = deg - 1; k >= 0; --k) q = fma(q, u, c[k]);
-    return fma(kTwoOverSqrtPi, x, q);
+    for (int k = deg - 2; k >= 0; --k) q = fma(q, t, m[k]);
+    return fma(a.g, x, q);
 }
 
-// e^{-y} for 0 <= y < 42.3: y = -n ln2 - f with n = rint(-y log2 e), |f| <= ln2 / 2
+// 2^z / lead_e for -61 < z <= 0: z = n + s, n = rint(z), |s| <= 1/2 (s exact), 2^s from the monic
+// polynomial of screening.h
 template <int Lv>
-__device__ inline double exp_neg_fast(double y, const PairArgs& a)
+__device__ inline double exp2_lead(double z, const PairArgs& a)
 {
-    const double n = rint(-y * kLog2e);
-    const double f = fma(n, -kLn2Lo, fma(n, -kLn2Hi, -y));
+    const double n = rint(z);
+    const double s = z - n;
     constexpr int deg = Lv == 1 ? kExpDeg1 : kExpDeg2;
-    const double* c = a.ce;
-    double p = c[deg];
+    const double* m = a.me;
+    double p = s + m[deg - 1];
 #pragma unroll
-    for (int k = deg - 1; k >= 0; --k) p = fma(p, f, c[k]);
+    for (int k = deg - 2; k >= 0; --k) p = fma(p, s, m[k]);
     return ldexp(p, (int)n);
 }
 
@@ -148,16 +155,17 @@ __device__ inline double rsqrt_pos(double r2)
     return fma(y * e, fma(0.375, e, 0.5), y);
 }
 
-// Coefficients of G^N(r) f = a1 f + b (r.f) r for 0 < r^2 < r_c^2 (FP64):
-// a1 = C/r - (4 xi/sqrt(pi)) e, b = C/r^3
+// Coefficients of G^N(r) f = a1 f + b (r.f) r for 0 < r^2 < r_c^2 (FP64), divided by post:
+// a1 = C/r - (4 xi/sqrt(pi)) e, b = C/r^3, with e = e^{-xi^2 r^2} = lead_e e' and C = e Q,
+// Q = lead_s Q'
 template <int Lv>
 __device__ inline void coef64(double r2, const PairArgs& a, double& a1, double& b)
 {
     const double rinv = rsqrt_pos<Lv>(r2);
     const double x = a.xi * r2 * rinv;
-    const double e = Lv > 0 ? exp_neg_fast<Lv>(a.xi2 * r2, a) : exp(-a.xi2 * r2);
+    const double e = Lv > 0 ? exp2_lead<Lv>(a.zc * r2, a) : exp(-a.xi2 * r2);
     const double Cr = e * screen_q64<Lv>(x, a) * rinv;
-    a1 = fma(-a.four_xi_over_sqrtpi, e, Cr);
+    a1 = fma(-a.h, e, Cr);
     b = Cr * (rinv * rinv);
 }
 
@@ -193,16 +201,19 @@ __device__ inline void coef32(double r2d, const PairArgs& a, float& a1, float& b
 // float: FP32 bulk, Lv unused).
 template <typename TF, int Lv>
 struct Coef;
+// post: the factor that the sums of eval's contributions take at the end
 template <int Lv>
 struct Coef<double, Lv> {
     __device__ static inline void eval(double r2, const PairArgs& a, double& a1, double& b)
     {
         coef64<Lv>(r2, a, a1, b);
     }
+    __device__ static inline double post(const PairArgs& a) { return a.post; }
 };
 template <int Lv>
 struct Coef<float, Lv> {
     __device__ static inline void eval(double r2, const PairArgs& a, float& a1, float& b) { coef32(r2, a, a1, b); }
+    __device__ static inline double post(const PairArgs&) { return 1.0; }
 };
 
 // Stresslet pair (combined single and double layer sources, Sec. 2.3): with the screened
@@ -218,8 +229,8 @@ __device__ inline void coef64_st(double r2, const PairArgs& a, double& a1, doubl
     const double rinv = rsqrt(r2);
     const double r = r2 * rinv;
     const double x = a.xi * r;
-    const double e = Lv > 0 ? exp_neg_fast<Lv>(a.xi2 * r2, a) : exp(-a.xi2 * r2);
-    const double C = e * screen_q64<Lv>(x, a);
+    const double e = Lv > 0 ? a.lead_e * exp2_lead<Lv>(a.zc * r2, a) : exp(-a.xi2 * r2);
+    const double C = e * (a.lead_s * screen_q64<Lv>(x, a));
     const double rinv2 = rinv * rinv, rinv3 = rinv2 * rinv;
     a1 = fma(C, rinv, -a.four_xi_over_sqrtpi * e);
     b = C * rinv3;
@@ -459,9 +470,10 @@ __global__ __launch_bounds__(64) void k_p2p(int n, const Rec64* __restrict__ rec
         return;
     }
     if (active) {
-        u_near[i] = (double)acc[0][lane];
-        u_near[(int64_t)n + i] = (double)acc[1][lane];
-        u_near[2 * (int64_t)n + i] = (double)acc[2][lane];
+        const double post = Coef<TF, Lv>::post(a);
+        u_near[i] = post * (double)acc[0][lane];
+        u_near[(int64_t)n + i] = post * (double)acc[1][lane];
+        u_near[2 * (int64_t)n + i] = post * (double)acc[2][lane];
     }
 }
 
@@ -594,6 +606,8 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
     }
     __syncthreads();
     const int mi = lane & 15, mk = lane >> 4;  // lane = 16 mk + mi
+    // the stresslet formula (CoefSt) returns its coefficients unscaled
+    const double post = ST ? 1.0 : Coef<TF, Lv>::post(a);
 
     int rhead = 0, rcount = 0;
     int tk = 0;  // neighbour tiles met so far (those within r_c of the targets)
@@ -729,9 +743,9 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
         const int own_all = wave_min_small(own_n);
         const TF mf0 = (TF)me.f[0], mf1 = (TF)me.f[1], mf2 = (TF)me.f[2];
         for (int r = 0; r < own_all; ++r) {
-            const int sl = (__ffs(rm) - 1 + rot) & (kB - 1);
+            const int sl = (__builtin_ctz(rm) + rot) & (kB - 1);
             rm &= rm - 1;
-            const int slot = (rhead + sl) & (kSymRing - 1);
+            const int slot = rhead + sl;
             TF c0, c1, c2, d0, d1, d2;
             pair(tx[0], tx[1], tx[2], mf0, mf1, mf2, lane, slot, c0, c1, c2, d0, d1, d2);
             oacc[0] += (double)c0;
@@ -753,11 +767,11 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
             qb += __popcll(bi);
             const bool don = !own && q < qx;
             const int e = queue[q < qx ? q : 0];
-            const int pb = __ffs(rm) - 1;
+            const int pb = __builtin_ctz(rm);  // used by own lanes only (rm != 0)
             rm = own ? (rm & (rm - 1)) : rm;
             const int tt = own ? lane : (e & (kWave - 1));
             const int sl = own ? ((pb + rot) & (kB - 1)) : ((e >> 6) & (kB - 1));
-            const int slot = (rhead + sl) & (kSymRing - 1);
+            const int slot = rhead + sl;
             TF c0, c1, c2, d0, d1, d2;
             pair(tgt[0][tt], tgt[1][tt], tgt[2][tt], tgtf[0][tt], tgtf[1][tt], tgtf[2][tt], tt, slot, c0, c1, c2,
                  d0, d1, d2);
@@ -793,9 +807,9 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
             }
             if (v0 != 0.0 || v1 != 0.0 || v2 != 0.0) {
                 const int64_t jj = ringk[slot] & (kFar - 1);
-                unsafeAtomicAdd(&u_near[jj], v0);
-                unsafeAtomicAdd(&u_near[(int64_t)n + jj], v1);
-                unsafeAtomicAdd(&u_near[2 * (int64_t)n + jj], v2);
+                unsafeAtomicAdd(&u_near[jj], post * v0);
+                unsafeAtomicAdd(&u_near[(int64_t)n + jj], post * v1);
+                unsafeAtomicAdd(&u_near[2 * (int64_t)n + jj], post * v2);
             }
         }
         __syncthreads();
@@ -885,9 +899,9 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
         rcount -= c;
     }
     if (active) {
-        unsafeAtomicAdd(&u_near[i], acc[0][lane] + oacc[0]);
-        unsafeAtomicAdd(&u_near[(int64_t)n + i], acc[1][lane] + oacc[1]);
-        unsafeAtomicAdd(&u_near[2 * (int64_t)n + i], acc[2][lane] + oacc[2]);
+        unsafeAtomicAdd(&u_near[i], post * (acc[0][lane] + oacc[0]));
+        unsafeAtomicAdd(&u_near[(int64_t)n + i], post * (acc[1][lane] + oacc[1]));
+        unsafeAtomicAdd(&u_near[2 * (int64_t)n + i], post * (acc[2][lane] + oacc[2]));
     }
 }
 
@@ -902,15 +916,21 @@ PairArgs pair_args(const Plan& pl, int lv)
     a.xi2 = pl.xi * pl.xi;
     a.rc2 = pl.rc * pl.rc;
     a.four_xi_over_sqrtpi = 4.0 * pl.xi / sqrt(M_PI);
-    a.xi2_log2e = a.xi2 * 1.4426950408889634;
+    a.xi2_log2e = a.xi2 * kLog2e;
     a.six_xi_over_sqrtpi = 6.0 * pl.xi / sqrt(M_PI);
     a.four_xi3_over_sqrtpi = 4.0 * pl.xi * pl.xi * pl.xi / sqrt(M_PI);
-    const double* cs = lv == 2 ? kScreenC64f : lv == 1 ? kScreenC64s : kScreenC64;
+    const double* ms = lv == 2 ? kScreenM64f : lv == 1 ? kScreenM64s : kScreenM64;
     const int ds = lv == 2 ? kScreenDeg64f : lv == 1 ? kScreenDeg64s : kScreenDeg64;
-    for (int k = 0; k <= kScreenDeg64; ++k) a.cs[k] = k <= ds ? cs[k] : 0.0;
-    const double* ce = lv == 2 ? kExpC2 : kExpC1;
+    for (int k = 0; k < kScreenDeg64; ++k) a.ms[k] = k < ds ? ms[k] : 0.0;
+    a.lead_s = lv == 2 ? kScreenLead64f : lv == 1 ? kScreenLead64s : kScreenLead64;
+    const double* me = lv == 2 ? kExpM2 : kExpM1;
     const int de = lv == 2 ? kExpDeg2 : kExpDeg1;
-    for (int k = 0; k <= kExpDeg1; ++k) a.ce[k] = k <= de ? ce[k] : 0.0;
+    for (int k = 0; k < kExpDeg1; ++k) a.me[k] = k < de ? me[k] : 0.0;
+    a.lead_e = lv == 0 ? 1.0 : lv == 2 ? kExpLead2 : kExpLead1;
+    a.zc = -a.xi2 * kLog2e;
+    a.g = kTwoOverSqrtPi / a.lead_s;
+    a.h = a.four_xi_over_sqrtpi / a.lead_s;
+    a.post = a.lead_s * a.lead_e;
     for (int k = 0; k <= kScreenDeg32; ++k) a.c32[k] = (float)kScreenC32[k];
     return a;
 }
