@@ -109,6 +109,18 @@ __device__ inline int lanes_below(unsigned long long m)
                                           __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
+// One LDS value per instruction: the compiler would pair two loads of a ring or target slot
+// (rows 512 bytes apart) into one ds_read2st64_b64, which occupies the LDS pipeline for 8 cycles
+// per wave on gfx950, twice as long as two ds_read_b64 (2 cycles each); the P2P kernels are bound
+// by LDS throughput.  A volatile access is never paired; the address-space cast keeps it a plain
+// LDS load (r must be an element of a __shared__ array).
+template <typename T>
+__device__ inline T ld1(const T& r)
+{
+    typedef __attribute__((address_space(3))) T LdsT;
+    return *(const volatile LdsT*)(const LdsT*)&r;
+}
+
 // (erfcx(x) + 2x/sqrt(pi)) / lead_s for 0 <= x <= kScreenXmax: the monic polynomial of screening.h
 // in t = (x - K)/(x + K) = 1 - 2K/(x + K), plus g x
 template <int Lv>
@@ -365,7 +377,7 @@ __global__ __launch_bounds__(64) void k_p2p(int n, const Rec64* __restrict__ rec
         int qn = 0;
         for (int j = 0; j < cnt; ++j) {
             const int slot = (rhead + j) & (kRing - 1);
-            const double rx = tx[0] - ring[0][slot], ry = tx[1] - ring[1][slot], rz = tx[2] - ring[2][slot];
+            const double rx = tx[0] - ld1(ring[0][slot]), ry = tx[1] - ld1(ring[1][slot]), rz = tx[2] - ld1(ring[2][slot]);
             const double r2 = rx * rx + ry * ry + rz * rz;
             const bool pass = (r2 < a.rc2) && (r2 > 0.0);
             const unsigned long long b = __ballot(pass);
@@ -384,13 +396,14 @@ __global__ __launch_bounds__(64) void k_p2p(int n, const Rec64* __restrict__ rec
                 const int e = queue[k];
                 const int tt = e & (kWave - 1);
                 const int slot = (rhead + (e >> 6)) & (kRing - 1);
-                const double rx = tgt[0][tt] - ring[0][slot];
-                const double ry = tgt[1][tt] - ring[1][slot];
-                const double rz = tgt[2][tt] - ring[2][slot];
+                const double rx = ld1(tgt[0][tt]) - ld1(ring[0][slot]);
+                const double ry = ld1(tgt[1][tt]) - ld1(ring[1][slot]);
+                const double rz = ld1(tgt[2][tt]) - ld1(ring[2][slot]);
                 const double r2 = rx * rx + ry * ry + rz * rz;
                 TF a1, b, c0, c1, c2;
                 Coef<TF, Lv>::eval(r2, a, a1, b);
-                apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, ringf[0][slot], ringf[1][slot], ringf[2][slot], c0, c1, c2);
+                apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, ld1(ringf[0][slot]), ld1(ringf[1][slot]), ld1(ringf[2][slot]), c0,
+                          c1, c2);
                 atomicAdd(&acc[0][tt], (TA)c0);
                 atomicAdd(&acc[1][tt], (TA)c1);
                 atomicAdd(&acc[2][tt], (TA)c2);
@@ -624,7 +637,7 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
         if (own_tile) {
             for (int j = 0; j < cnt; ++j) {
                 const int slot = (rhead + j) & (kSymRing - 1);
-                const double rx = tx[0] - ring[0][slot], ry = tx[1] - ring[1][slot], rz = tx[2] - ring[2][slot];
+                const double rx = tx[0] - ld1(ring[0][slot]), ry = tx[1] - ld1(ring[1][slot]), rz = tx[2] - ld1(ring[2][slot]);
                 const double r2 = rx * rx + ry * ry + rz * rz;
                 const bool pass = (r2 < a.rc2) & (r2 > 0.0) & (ringk[slot] > i);
                 m = pass ? (m | (1u << j)) : m;
@@ -644,7 +657,7 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
 #pragma unroll
             for (int mb = 0; mb < 2; ++mb) {
                 const int slot = rhead + 16 * mb + 4 * (mi & 3) + (mi >> 2);
-                const double x0 = ring[0][slot], x1 = ring[1][slot], x2 = ring[2][slot];
+                const double x0 = ld1(ring[0][slot]), x1 = ld1(ring[1][slot]), x2 = ld1(ring[2][slot]);
                 av[mb] = mk == 0 ? x0 : mk == 1 ? x1 : mk == 2 ? x2 : fma(x0, x0, fma(x1, x1, x2 * x2));
             }
             // column block nb: targets 16 nb + i; operand B[kq][i] = -2 t'_kq (kq = 3: 1).  The bits of
@@ -676,7 +689,7 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
         } else {
             for (int j = 0; j < cnt; ++j) {
                 const int slot = (rhead + j) & (kSymRing - 1);
-                const double rx = tx[0] - ring[0][slot], ry = tx[1] - ring[1][slot], rz = tx[2] - ring[2][slot];
+                const double rx = tx[0] - ld1(ring[0][slot]), ry = tx[1] - ld1(ring[1][slot]), rz = tx[2] - ld1(ring[2][slot]);
                 const bool pass = rx * rx + ry * ry + rz * rz < a.rc2;
                 m = pass ? (m | (1u << j)) : m;
                 qn += __popcll(ballot(pass));
@@ -712,27 +725,29 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
         // the target, d = G^N(-r) f_target for the source (r = p - x_source)
         auto pair = [&](double p0, double p1, double p2, TF tf0, TF tf1, TF tf2, int tt, int slot, TF& c0,
                         TF& c1, TF& c2, TF& d0, TF& d1, TF& d2) {
-            const double rx = p0 - ring[0][slot];
-            const double ry = p1 - ring[1][slot];
-            const double rz = p2 - ring[2][slot];
+            const double rx = p0 - ld1(ring[0][slot]);
+            const double ry = p1 - ld1(ring[1][slot]);
+            const double rz = p2 - ld1(ring[2][slot]);
             const double r2 = rx * rx + ry * ry + rz * rz;
             TF a1, b;
             if constexpr (ST) {
                 TF al, be;
                 CoefSt<TF, Lv>::eval(r2, a, a1, b, al, be);
-                apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, ringf[0][slot], ringf[1][slot], ringf[2][slot], c0, c1, c2);
+                apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, ld1(ringf[0][slot]), ld1(ringf[1][slot]), ld1(ringf[2][slot]), c0,
+                          c1, c2);
                 apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, tf0, tf1, tf2, d0, d1, d2);
                 TF ss[6], st[6];
 #pragma unroll
                 for (int c = 0; c < 6; ++c) {
-                    ss[c] = rings[c][slot];
-                    st[c] = -tgts[c][tt];  // T^N(-r) = -T^N(r)
+                    ss[c] = ld1(rings[c][slot]);
+                    st[c] = -ld1(tgts[c][tt]);  // T^N(-r) = -T^N(r)
                 }
                 apply_st<TF>(al, be, (TF)rx, (TF)ry, (TF)rz, ss, c0, c1, c2);
                 apply_st<TF>(al, be, (TF)rx, (TF)ry, (TF)rz, st, d0, d1, d2);
             } else {
                 Coef<TF, Lv>::eval(r2, a, a1, b);
-                apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, ringf[0][slot], ringf[1][slot], ringf[2][slot], c0, c1, c2);
+                apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, ld1(ringf[0][slot]), ld1(ringf[1][slot]), ld1(ringf[2][slot]), c0,
+                          c1, c2);
                 apply<TF>(a1, b, (TF)rx, (TF)ry, (TF)rz, tf0, tf1, tf2, d0, d1, d2);
             }
         };
@@ -773,8 +788,8 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
             const int sl = own ? ((pb + rot) & (kB - 1)) : ((e >> 6) & (kB - 1));
             const int slot = rhead + sl;
             TF c0, c1, c2, d0, d1, d2;
-            pair(tgt[0][tt], tgt[1][tt], tgt[2][tt], tgtf[0][tt], tgtf[1][tt], tgtf[2][tt], tt, slot, c0, c1, c2,
-                 d0, d1, d2);
+            pair(ld1(tgt[0][tt]), ld1(tgt[1][tt]), ld1(tgt[2][tt]), ld1(tgtf[0][tt]), ld1(tgtf[1][tt]),
+                 ld1(tgtf[2][tt]), tt, slot, c0, c1, c2, d0, d1, d2);
             if (own) {
                 oacc[0] += (double)c0;
                 oacc[1] += (double)c1;
