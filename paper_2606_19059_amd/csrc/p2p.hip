@@ -102,6 +102,31 @@ __device__ inline int wave_min_small(int v)
     return lo;
 }
 
+// position of the k-th (from 0) set bit of m, for k < popcount(m): five halving steps
+__device__ inline int select_bit(unsigned m, int k)
+{
+    int pos = 0;
+#pragma unroll
+    for (int s = 16; s >= 1; s >>= 1) {
+        const int low = __popc(m & ((1u << s) - 1u));
+        const bool up = low <= k;
+        k = up ? k - low : k;
+        m = up ? m >> s : m;
+        pos = up ? pos + s : pos;
+    }
+    return pos;
+}
+
+// v | (v of lane l ^ 16) | (v of lane l ^ 32) | (v of lane l ^ 48), by the lane-swap instructions
+// (VALU; a shuffle would take the LDS pipeline, which bounds the P2P kernels)
+__device__ inline unsigned or_rows4(unsigned v)
+{
+    const auto a = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    v = a[0] | a[1];
+    const auto b = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return b[0] | b[1];
+}
+
 // number of set bits of m in the lanes below this one
 __device__ inline int lanes_below(unsigned long long m)
 {
@@ -681,8 +706,7 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
                     }
                     wv |= nib << (16 * mb + 4 * mk);
                 }
-                wv |= (unsigned)__shfl_xor((int)wv, 16, kWave);
-                wv |= (unsigned)__shfl_xor((int)wv, 32, kWave);
+                wv = or_rows4(wv);
                 m = mk == nb ? wv : m;
                 __builtin_amdgcn_sched_barrier(0);
             }
@@ -696,13 +720,16 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
             }
         }
         const int rounds = (qn + kWave - 1) / kWave;
-        // 2. a lane keeps up to `rounds` of its target's pairs (taken in an order rotated by
-        //    lane mod 32, to spread a round's sources); the excess goes to the queue, for
-        //    lanes that run out of pairs of their own
-        const int rot = lane & (kB - 1);
+        // 2. a lane keeps up to `rounds` of its target's pairs, taken in cyclic order from its
+        //    (lane mod c)-th accepted source (c: its number of pairs), so that the lanes of a
+        //    half-wave start on different sources even when their accepted sets are alike (a
+        //    rotation by the lane number alone sent the lanes whose start lies outside a common
+        //    band of accepted sources to the band's first source together: same-address LDS
+        //    atomics); the excess goes to the queue, for lanes that run out of pairs of their own
+        const int c = __popc(m);
+        const int rot = c ? select_bit(m, lane % c) : 0;
         const unsigned rm0 = rot ? ((m >> rot) | (m << (kB - rot))) : m;
         unsigned rm = rm0;
-        const int c = __popc(m);
         const int own_n = c < rounds ? c : rounds;
         int ex = c - own_n;
         int qx = 0;
@@ -774,8 +801,7 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
         //     pairs, then queue entries in order (target side by LDS atomics)
         int qb = 0;
         for (int r = own_all; r < rounds; ++r) {
-            // branch-free round: every lane reads a queue entry (in range, used only by
-            // donated lanes) and its target's data from LDS (its own target for own lanes)
+            // every lane reads a queue entry (in range, used only by donated lanes)
             const bool own = r < own_n;
             const unsigned long long bi = ballot(!own);
             const int q = qb + lanes_below(bi);
@@ -787,9 +813,20 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
             const int tt = own ? lane : (e & (kWave - 1));
             const int sl = own ? ((pb + rot) & (kB - 1)) : ((e >> 6) & (kB - 1));
             const int slot = rhead + sl;
+            // own lanes take their target from registers, donated lanes from LDS (the volatile
+            // loads stay under the branch, so own lanes add no LDS traffic)
+            double q0 = tx[0], q1 = tx[1], q2 = tx[2];
+            TF g0 = mf0, g1 = mf1, g2 = mf2;
+            if (!own) {
+                q0 = ld1(tgt[0][tt]);
+                q1 = ld1(tgt[1][tt]);
+                q2 = ld1(tgt[2][tt]);
+                g0 = ld1(tgtf[0][tt]);
+                g1 = ld1(tgtf[1][tt]);
+                g2 = ld1(tgtf[2][tt]);
+            }
             TF c0, c1, c2, d0, d1, d2;
-            pair(ld1(tgt[0][tt]), ld1(tgt[1][tt]), ld1(tgt[2][tt]), ld1(tgtf[0][tt]), ld1(tgtf[1][tt]),
-                 ld1(tgtf[2][tt]), tt, slot, c0, c1, c2, d0, d1, d2);
+            pair(q0, q1, q2, g0, g1, g2, tt, slot, c0, c1, c2, d0, d1, d2);
             if (own) {
                 oacc[0] += (double)c0;
                 oacc[1] += (double)c1;
