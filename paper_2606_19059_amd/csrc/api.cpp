@@ -221,12 +221,12 @@ double model_ms(int mode, bool grid64, double n, const double box[3], const int 
     const double V = box[0] * box[1] * box[2];
     const double cells = (double)M[0] * M[1] * M[2];
     const double pairs = 0.5 * n * n / V * (4.0 / 3.0) * M_PI * rc * rc * rc;
-    // P2P waves: one per 64-target chunk (about n/64 + tiles/2), three per chunk when the
-    // launch has few chunks, four when it has very few (the rule of launch_p2p in p2p.hip, on
-    // its grid of tiles + n/64 chunks: fewer than 40000, fewer than 2048)
+    // P2P waves: three per 64-target chunk (about n/64 + tiles/2 chunks), six when the launch
+    // has very few (the rule of launch_p2p in p2p.hip, on its grid of tiles + n/64 chunks: fewer
+    // than 2048)
     const double tiles = cells / ((double)B * B * B);
     const double grid_waves = tiles + std::ceil(n / 64.0);
-    const double split = grid_waves < 2048.0 ? 4.0 : grid_waves < 40000.0 ? 3.0 : 1.0;
+    const double split = grid_waves < 2048.0 ? 6.0 : 3.0;
     const double waves = (n / 64.0 + 0.5 * tiles) * split;
     const double np3 = n * P * P * P;
     // G2P: groups of 16 targets of one tile; each runs ceil(U^2 / 4) x NB matrix steps, U = P - 1 +

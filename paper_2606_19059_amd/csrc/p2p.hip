@@ -1045,12 +1045,12 @@ hipError_t launch_p2p(const Plan& pl, const Work& w, int n, hipStream_t s, bool 
         }
         return hipGetLastError();
     }
-    // Symmetric kernel: with few chunks per wave slot of the chip (c2: 15.6k chunks, about 4 per
-    // slot), three waves per chunk shorten the waves and so the launch's tail (measured at c2:
-    // 25.5 -> 24.2 ms; two: 24.5, four: 25.3; again with the matrix-core cutoff test: three 21.4,
-    // two 21.6, four 22.4 ms); with many (c3: 156k) one (two and four were slower there); with
-    // fewer chunks than wave slots, four (c1, N = 1e3: 0.097 -> 0.071 ms).
-    const int kSplit = waves < 2048 ? 4 : waves < 40000 ? 3 : 1;
+    // Symmetric kernel: three waves per chunk (each taking every third neighbour tile) shorten the
+    // waves and so the launch's tail.  Measured P2P ms for 1 / 2 / 3 / 4 / 6 waves per chunk: c2
+    // (17k chunks) 20.1 / 18.7 / 18.5 / 19.5 / 18.7; H 10.8 / 10.4 / 10.1 / 11.6 / 10.4; c4 (63k)
+    // 51.7 / 51.4 / 50.9 / 55.6 / 52.1; clustered c3 (160k) 172.7 / 177.6 / 172.2 / 231.8 / 182.2.
+    // With fewer chunks than wave slots, six (c1, N = 1e3: 0.158 / 0.093 / 0.098 / 0.072 / 0.063).
+    const int kSplit = waves < 2048 ? 6 : 3;
     const dim3 sgrid((unsigned)(waves * kSplit));
     const int64_t cnt = 3 * (int64_t)n;
     hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, w.u_near, cnt);
