@@ -24,6 +24,7 @@
 //      result is added to its target's FP64 accumulator in LDS with ds_add_f64 (the pairs
 //      of one source have distinct targets, so conflicts are few).
 #include "internal.h"
+#include <type_traits>
 #include "screening.h"
 
 namespace ewald {
@@ -783,13 +784,35 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
         //     at uniform density): no queue, no ballot, and the target's position and force
         //     come from registers
         const int own_all = wave_min_small(own_n);
-        const TF mf0 = (TF)me.f[0], mf1 = (TF)me.f[1], mf2 = (TF)me.f[2];
+        // the lane's target (position, force).  At the reduced-cost FP64 levels the all-own rounds
+        // sum the target side straight into the FMAs, and a lane that runs out of pairs of its
+        // own overwrites these registers with a donated pair's target in the queue rounds (c2
+        // P2P -1.4%); at level 0 and in FP32 both cost more registers or time than they save
+        constexpr bool kRegTarget = std::is_same<TF, double>::value && Lv > 0;
+        double px = tx[0], py = tx[1], pz = tx[2];
+        TF mf0 = (TF)me.f[0], mf1 = (TF)me.f[1], mf2 = (TF)me.f[2];
         for (int r = 0; r < own_all; ++r) {
             const int sl = (__builtin_ctz(rm) + rot) & (kB - 1);
             rm &= rm - 1;
             const int slot = rhead + sl;
+            if constexpr (!ST && kRegTarget) {
+                // the target side summed straight into the FMAs: oacc += a1 f_s + b (r.f_s) r
+                const double rx = px - ld1(ring[0][slot]), ry = py - ld1(ring[1][slot]), rz = pz - ld1(ring[2][slot]);
+                double a1, b;
+                Coef<double, Lv>::eval(rx * rx + ry * ry + rz * rz, a, a1, b);
+                const double s0 = ld1(ringf[0][slot]), s1 = ld1(ringf[1][slot]), s2 = ld1(ringf[2][slot]);
+                const double rs = (rx * s0 + ry * s1 + rz * s2) * b;
+                oacc[0] = fma(rs, rx, fma(a1, s0, oacc[0]));
+                oacc[1] = fma(rs, ry, fma(a1, s1, oacc[1]));
+                oacc[2] = fma(rs, rz, fma(a1, s2, oacc[2]));
+                const double rt = (rx * mf0 + ry * mf1 + rz * mf2) * b;
+                atomicAdd(&racc[0][rq][sl], fma(a1, mf0, rt * rx));
+                atomicAdd(&racc[1][rq][sl], fma(a1, mf1, rt * ry));
+                atomicAdd(&racc[2][rq][sl], fma(a1, mf2, rt * rz));
+                continue;
+            }
             TF c0, c1, c2, d0, d1, d2;
-            pair(tx[0], tx[1], tx[2], mf0, mf1, mf2, lane, slot, c0, c1, c2, d0, d1, d2);
+            pair(px, py, pz, mf0, mf1, mf2, lane, slot, c0, c1, c2, d0, d1, d2);
             oacc[0] += (double)c0;
             oacc[1] += (double)c1;
             oacc[2] += (double)c2;
@@ -809,28 +832,51 @@ __global__ __launch_bounds__(64) void k_p2p_sym(int n, const Rec64* __restrict__
             const bool don = !own && q < qx;
             const int e = queue[q < qx ? q : 0];
             const int pb = __builtin_ctz(rm);  // used by own lanes only (rm != 0)
-            rm = own ? (rm & (rm - 1)) : rm;
+            if constexpr (!kRegTarget) rm = own ? (rm & (rm - 1)) : rm;
             const int tt = own ? lane : (e & (kWave - 1));
             const int sl = own ? ((pb + rot) & (kB - 1)) : ((e >> 6) & (kB - 1));
             const int slot = rhead + sl;
             // own lanes take their target from registers, donated lanes from LDS (the volatile
             // loads stay under the branch, so own lanes add no LDS traffic)
-            double q0 = tx[0], q1 = tx[1], q2 = tx[2];
-            TF g0 = mf0, g1 = mf1, g2 = mf2;
-            if (!own) {
-                q0 = ld1(tgt[0][tt]);
-                q1 = ld1(tgt[1][tt]);
-                q2 = ld1(tgt[2][tt]);
-                g0 = ld1(tgtf[0][tt]);
-                g1 = ld1(tgtf[1][tt]);
-                g2 = ld1(tgtf[2][tt]);
-            }
             TF c0, c1, c2, d0, d1, d2;
-            pair(q0, q1, q2, g0, g1, g2, tt, slot, c0, c1, c2, d0, d1, d2);
-            if (own) {
-                oacc[0] += (double)c0;
-                oacc[1] += (double)c1;
-                oacc[2] += (double)c2;
+            if constexpr (kRegTarget) {
+                // a lane that is not own in this round is not own in any later one: it
+                // overwrites its target registers
+                if (!own) {
+                    px = ld1(tgt[0][tt]);
+                    py = ld1(tgt[1][tt]);
+                    pz = ld1(tgt[2][tt]);
+                    mf0 = ld1(tgtf[0][tt]);
+                    mf1 = ld1(tgtf[1][tt]);
+                    mf2 = ld1(tgtf[2][tt]);
+                }
+                pair(px, py, pz, mf0, mf1, mf2, tt, slot, c0, c1, c2, d0, d1, d2);
+                if (own) {
+                    // an empty volatile asm keeps this a branch (the if-converted form takes
+                    // two selects per component)
+                    asm volatile("");
+                    oacc[0] += (double)c0;
+                    oacc[1] += (double)c1;
+                    oacc[2] += (double)c2;
+                    rm &= rm - 1;
+                }
+            } else {
+                double q0 = px, q1 = py, q2 = pz;
+                TF g0 = mf0, g1 = mf1, g2 = mf2;
+                if (!own) {
+                    q0 = ld1(tgt[0][tt]);
+                    q1 = ld1(tgt[1][tt]);
+                    q2 = ld1(tgt[2][tt]);
+                    g0 = ld1(tgtf[0][tt]);
+                    g1 = ld1(tgtf[1][tt]);
+                    g2 = ld1(tgtf[2][tt]);
+                }
+                pair(q0, q1, q2, g0, g1, g2, tt, slot, c0, c1, c2, d0, d1, d2);
+                if (own) {
+                    oacc[0] += (double)c0;
+                    oacc[1] += (double)c1;
+                    oacc[2] += (double)c2;
+                }
             }
             if (don) {
                 atomicAdd(&acc[0][tt], (double)c0);
