@@ -60,6 +60,7 @@ struct PairArgs {
     double ms[kScreenDeg64];
     double me[kExpDeg1];
     float c32[kScreenDeg32 + 1];
+    float zc32;  // FP32 formula: -xi^2 log2 e
     double six_xi_over_sqrtpi, four_xi3_over_sqrtpi;  // stresslet screening
 };
 
@@ -208,9 +209,11 @@ __device__ inline void coef64(double r2, const PairArgs& a, double& a1, double& 
 }
 
 // FP32 versions (FP32 bulk mode): hardware reciprocal, rsqrt and exp2 (1 ulp each, used
-// as they come: a refinement step would only chase FP32's own rounding), degree-11 polynomial.  The exponent -xi^2 r^2 log2(e) reaches ~40, where one FP32 ulp is
-// ~4e-6, so it is formed and split into integer and fraction in FP64 (same VALU rate) and
-// only 2^fraction is taken in FP32.
+// as they come: a refinement step would only chase FP32's own rounding), degree-11
+// polynomial.  e = 2^z with z = -xi^2 r^2 log2(e) formed in FP32: z reaches -61, where its
+// rounding moves 2^z by up to 3e-6 relative, but the absolute error, 2^z |z| ln2 x 2^-24, stays
+// below 8e-8 over the whole range (as for FP32 rounding of e itself); e multiplies the field
+// terms, so this is the error that counts.
 __device__ inline float screen_q32(float x, const PairArgs& a)
 {
     const float d = x + (float)kScreenK;
@@ -227,9 +230,7 @@ __device__ inline void coef32(double r2d, const PairArgs& a, float& a1, float& b
     const float r2 = (float)r2d;
     const float rinv = __builtin_amdgcn_rsqf(r2);  // 1 ulp: no refinement needed in FP32
     const float x = (float)a.xi * r2 * rinv;
-    const double ea = -a.xi2_log2e * r2d;
-    const double en = rint(ea);
-    const float e = ldexpf(__builtin_amdgcn_exp2f((float)(ea - en)), (int)en);
+    const float e = __builtin_amdgcn_exp2f(a.zc32 * r2);
     const float Cr = e * screen_q32(x, a) * rinv;
     a1 = fmaf(-(float)a.four_xi_over_sqrtpi, e, Cr);
     b = Cr * (rinv * rinv);
@@ -283,9 +284,7 @@ __device__ inline void coef32_st(double r2d, const PairArgs& a, float& a1, float
     const float rinv = __builtin_amdgcn_rsqf(r2);
     const float r = r2 * rinv;
     const float x = (float)a.xi * r;
-    const double ea = -a.xi2_log2e * r2d;
-    const double en = rint(ea);
-    const float e = ldexpf(__builtin_amdgcn_exp2f((float)(ea - en)), (int)en);
+    const float e = __builtin_amdgcn_exp2f(a.zc32 * r2);
     const float C = e * screen_q32(x, a);
     const float rinv2 = rinv * rinv, rinv3 = rinv2 * rinv;
     a1 = fmaf(C, rinv, -(float)a.four_xi_over_sqrtpi * e);
@@ -1026,6 +1025,7 @@ PairArgs pair_args(const Plan& pl, int lv)
     for (int k = 0; k < kExpDeg1; ++k) a.me[k] = k < de ? me[k] : 0.0;
     a.lead_e = lv == 0 ? 1.0 : lv == 2 ? kExpLead2 : kExpLead1;
     a.zc = -a.xi2 * kLog2e;
+    a.zc32 = (float)a.zc;
     a.g = kTwoOverSqrtPi / a.lead_s;
     a.h = a.four_xi_over_sqrtpi / a.lead_s;
     a.post = a.lead_s * a.lead_e;
