@@ -1,7 +1,8 @@
 """Host-side model of the balanced drain schedule of the symmetric P2P kernel
 (`k_p2p_sym`, Stokeslet-only form): per batch of 32 ring entries a lane keeps up to
-R = ceil(Q / 64) pairs of its own target, taken in an order rotated by lane mod 32 (lowest
-rotated bit first), and queues the rest (highest rotated bits first); lanes with fewer
+R = ceil(Q / 64) pairs of its own target, taken in cyclic order starting at its
+(lane mod c)-th accepted entry (c its pair count; lowest rotated bit first), and queues the
+rest (highest rotated bits first); lanes with fewer
 than R pairs take queue entries in order in their spare rounds.  The first min over lanes
 of the own-pair counts are rounds in which every lane takes its own pair; the kernel runs
 them as a separate loop (no ballot, no queue) and starts the general rounds after them.
@@ -20,7 +21,11 @@ def schedule(acc):
     m = [sum(int(acc[l, j]) << j for j in range(cnt)) for l in range(LANES)]
     qn = int(acc.sum())
     rounds = (qn + LANES - 1) // LANES
-    rot = [l & (K - 1) for l in range(LANES)]
+    # start of each lane's cyclic order: its (lane mod c)-th set bit (0 for an empty mask)
+    rot = []
+    for l in range(LANES):
+        bits = [j for j in range(K) if m[l] >> j & 1]
+        rot.append(bits[l % len(bits)] if bits else 0)
     rm = [((m[l] >> rot[l]) | (m[l] << (K - rot[l]))) & 0xFFFFFFFF for l in range(LANES)]
     c = [bin(x).count("1") for x in m]
     own_n = [min(x, rounds) for x in c]
