@@ -534,10 +534,11 @@ __global__ __launch_bounds__(64) void k_p2p(int n, const Rec64* __restrict__ rec
 // of one pair per lane; a lane keeps up to R pairs of its own target (summed in registers)
 // and puts the rest in a queue, from which lanes with fewer than R pairs take work in their
 // spare rounds (target side by LDS atomics, about 15% of the pairs at uniform density).
-// Lanes take their own sources in an order rotated by lane mod 32, so that lanes t and
-// t + 32 aside, the lanes meet different sources in a round when their masks are full
-// (fewer collisions on the batch's source accumulators).  With stresslet sources the same
-// schedule carries the stresslet pair terms as well.
+// Each lane takes its own sources in cyclic order from its (lane mod c)-th accepted one (c its
+// pair count), so that the lanes of a half-wave start on different sources also when their
+// accepted sets are alike (fewer collisions on the batch's source accumulators).  The ring
+// and target slots are read one value per LDS instruction (ld1).  With stresslet sources the
+// same schedule carries the stresslet pair terms as well.
 //
 // Cutoff test on the matrix cores.  The targets' positions t' and the ring's sources s' are taken
 // relative to the centre of the targets' bounding box, so that |s' - t'|^2 < r_c^2 can be tested
