@@ -84,12 +84,18 @@ def stage_roofline(stages, n, ncell, P, real, pairs, alu_peak_tflops):
 
 
 def kernel_source_hash():
+    """SHA-256 of the P2P kernel's sources with comments and blank space removed (a change of
+    comments alone leaves the counters valid)."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     for name in P2P_SOURCES:
-        with open(os.path.join(ROOT, "paper_2606_19059_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2606_19059_amd", "csrc", name)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 
