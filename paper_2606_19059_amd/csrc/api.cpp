@@ -200,9 +200,9 @@ struct CostModel {
     double fft_cell, fft0;
     double sort, sort_cell, sort0;
 };
-constexpr CostModel kCost64 = {6.437, 0.199, 0.108, 0.169, 0.072, 43.585, 2.914, 0.0039, 0.0, 0.086, 0.028,
+constexpr CostModel kCost64 = {5.217, 0.053, 0.108, 0.169, 0.072, 43.585, 2.914, 0.0039, 0.0, 0.076, 0.030,
                                0.216, 0.008, 0.044};
-constexpr CostModel kCost32 = {5.462, 0.245, 0.146, 0.171, 0.059, 53.008, 2.957, 0.0, 0.0041, 0.055, 0.037,
+constexpr CostModel kCost32 = {4.423, 0.045, 0.146, 0.171, 0.059, 53.008, 2.957, 0.0, 0.0041, 0.048, 0.042,
                                0.223, 0.006, 0.044};
 constexpr double kWaveSlots = 2048.0;  // concurrent P2P waves at which the chip is full
 
