@@ -259,8 +259,9 @@ __global__ __launch_bounds__(kWaves * 64) void k_p2g_sweep(const typename RecVie
             wave_lds_sync();
 #pragma unroll 2
             for (int q = q0; q < q0 + cnt; ++q) {
-                const T wy = swy[q][ly];
-                const T g0 = wy * swz[q][0][lz], g1 = wy * swz[q][1][lz], g2 = wy * swz[q][2][lz];
+                // single-value LDS loads (a paired load occupies the LDS pipeline twice as long)
+                const T wy = ld1(swy[q][ly]);
+                const T g0 = wy * ld1(swz[q][0][lz]), g1 = wy * ld1(swz[q][1][lz]), g2 = wy * ld1(swz[q][2][lz]);
 #pragma unroll
                 for (int k = 0; k < P; ++k) {
                     const T wx = swx[q][k];

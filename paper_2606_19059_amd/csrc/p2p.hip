@@ -136,18 +136,6 @@ __device__ inline int lanes_below(unsigned long long m)
                                           __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
-// One LDS value per instruction: the compiler would pair two loads of a ring or target slot
-// (rows 512 bytes apart) into one ds_read2st64_b64, which occupies the LDS pipeline for 8 cycles
-// per wave on gfx950, twice as long as two ds_read_b64 (2 cycles each); the P2P kernels are bound
-// by LDS throughput.  A volatile access is never paired; the address-space cast keeps it a plain
-// LDS load (r must be an element of a __shared__ array).
-template <typename T>
-__device__ inline T ld1(const T& r)
-{
-    typedef __attribute__((address_space(3))) T LdsT;
-    return *(const volatile LdsT*)(const LdsT*)&r;
-}
-
 // (erfcx(x) + 2x/sqrt(pi)) / lead_s for 0 <= x <= kScreenXmax: the monic polynomial of screening.h
 // in t = (x - K)/(x + K) = 1 - 2K/(x + K), plus g x
 template <int Lv>
