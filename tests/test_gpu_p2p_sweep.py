@@ -5,8 +5,9 @@ real-space sum and spectral far field (element by element).
 The sizes straddle the 64-target chunks (1, 63, 64, 65, 2047, 2049 ...); the distributions put
 many particles in one tile (dense batches: the balanced drain's queue and extra rounds),
 leave most tiles empty, or repeat positions.  FP64 plans use the full-precision pair formula
-(tol < 1e-10): 1e-12 of the array's max; FP32-bulk plans: 2e-6 (FP32 pair terms accumulated in
-FP64).  Stresslet sources are checked on a subset the same way."""
+(tol < 1e-10): 1e-12 of the array's max; the same FP64 cases at tol 1e-9 and 1e-7 run the
+reduced-cost formulas (1e-10 and 1e-9 of the max); FP32-bulk plans: 2e-6 (FP32 pair terms
+accumulated in FP64).  Stresslet sources are checked on a subset the same way."""
 import numpy as np
 import pytest
 
@@ -87,6 +88,28 @@ def test_p2p_sweep_matches_oracle(case):
     err = maxrel(host(un), ref) if np.max(np.abs(ref)) > 0 else float(np.max(np.abs(host(un))))
     bound = 1e-12 if prec == "fp64" else 2e-6
     print("P2P sweep %d: n %d %s %s %s: max rel err %.2e" % (case, n, kind, prec, grid, err))
+    assert err < bound
+
+
+# the reduced-cost FP64 pair formulas (accuracy levels 1 and 2, chosen from the plan's tol), with
+# the bound each level's formula error allows: level 1 (1e-10 <= tol < 1e-8) 1e-10, level 2 1e-9
+LEVELS = [(1e-9, 1e-10), (1e-7, 1e-9)]
+
+
+@pytest.mark.parametrize("case", [c for c in range(len(SWEEP)) if SWEEP[c][6] == "fp64"])
+@pytest.mark.parametrize("level", range(len(LEVELS)))
+def test_p2p_sweep_reduced_levels_match_oracle(case, level):
+    E = _E()
+    n, box, grid, xi, rc, kind, prec = SWEEP[case]
+    tol, bound = LEVELS[level]
+    rng = np.random.default_rng(400 + case)
+    x = positions(kind, n, box, rng)
+    f = W.mean_free_forces(rng, n) if n > 1 else rng.standard_normal((3, n))
+    pl = E.Plan(box, tol, xi=xi, r_c=rc, grid=grid, P=8, n_max=n, precision=prec)
+    un, _ = pl.eval_parts(dev(x), dev(f))
+    ref = oracle.real_space(x, f, box, xi, rc)
+    err = maxrel(host(un), ref) if np.max(np.abs(ref)) > 0 else float(np.max(np.abs(host(un))))
+    print("P2P sweep %d at tol %g: n %d %s %s: max rel err %.2e" % (case, tol, n, kind, grid, err))
     assert err < bound
 
 
