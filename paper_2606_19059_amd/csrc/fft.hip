@@ -25,8 +25,11 @@ namespace ewald {
 
 namespace {
 
+// aligned to its size, so that one complex value is one 16-byte (FP64) or 8-byte (FP32) access:
+// a pair of 8-byte LDS loads (ds_read2_b64) occupies the LDS pipeline twice as long as one
+// ds_read_b128 on gfx950
 template <typename T>
-struct C2 {
+struct alignas(2 * sizeof(T)) C2 {
     T x, y;
 };
 
@@ -124,7 +127,7 @@ __global__ __launch_bounds__(256) void k_fft_z(T* __restrict__ grid, int64_t nce
                                                int ncols, int sign, const C2<T>* __restrict__ tw_half,
                                                const C2<T>* __restrict__ tw_full)
 {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     // rows padded to ncols + 1 elements: a line's consecutive elements, which consecutive
     // threads load and store, then fall in different LDS banks (with a power-of-two row
     // stride they would all hit a few banks)
@@ -193,7 +196,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_fft_y(T* __restrict__ grid, int64_t ncells, int M2, int H,
                                                int ncols, int sign, const C2<T>* __restrict__ tw)
 {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T>* a = reinterpret_cast<C2<T>*>(smem_raw);
     C2<T>* b = a + (size_t)M2 * ncols;
     C2<T>* data = reinterpret_cast<C2<T>*>(grid + blockIdx.y * ncells);
@@ -233,7 +236,7 @@ __global__ __launch_bounds__(256) void k_fft_x_cnv(T* __restrict__ grid, int64_t
                                                    int H, int ncols, int do_cnv, int do_inv,
                                                    const C2<T>* __restrict__ tw, CnvArgs ca)
 {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int per = M1 * ncols;  // elements per component (power of two)
     C2<T>* a = reinterpret_cast<C2<T>*>(smem_raw);
     C2<T>* b = a + (size_t)3 * per;
@@ -301,7 +304,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_cnv_st_x(T* __restrict__ grid, int64_t ncells, int M1, int M2, int H,
                                                   int ncols, const C2<T>* __restrict__ tw, CnvArgs ca)
 {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int per = M1 * ncols;
     C2<T>* a = reinterpret_cast<C2<T>*>(smem_raw);
     C2<T>* b = a + (size_t)3 * per;
