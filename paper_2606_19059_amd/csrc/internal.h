@@ -139,7 +139,7 @@ struct Plan {
 
 // Device pointers carved out of the caller's workspace.
 struct Work {
-    int* key;        // [n]   sort key of each input particle
+    int* key;        // [n]   sort key of each input particle; after the sort, its sorted position
     int* perm;       // [n]   sorted slot -> original index (also carried in records)
     int* count;      // [ncells]   histogram, then scatter cursor
     int* start;      // [ncells+1] exclusive scan of count

@@ -227,12 +227,21 @@ __global__ void __launch_bounds__(kBigThreads) k_sort_big_cells(const int* __res
     }
 }
 
-__global__ void k_gather64(int n, const double* __restrict__ x, const double* __restrict__ f,
-                           const int* __restrict__ perm, Geometry g, Rec64* __restrict__ rec)
+// inv[perm[s]] = s: the sorted position of each input particle.  The gathers below then read the
+// caller's (3, N) arrays in their own order (coalesced) and write each whole record to its sorted
+// position; gathering through perm instead reads six arrays at random positions, which costs a full
+// memory segment per 8-byte value (15 times the bytes used at 1e6 uniform particles).
+__global__ void k_invert(int n, const int* __restrict__ perm, int* __restrict__ inv)
 {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const int i = perm[s];
+    if (s < n) inv[perm[s]] = s;
+}
+
+__global__ void k_gather64(int n, const double* __restrict__ x, const double* __restrict__ f,
+                           const int* __restrict__ inv, Geometry g, Rec64* __restrict__ rec)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
     Rec64 r;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -241,20 +250,19 @@ __global__ void k_gather64(int n, const double* __restrict__ x, const double* __
         r.f[d] = f[(int64_t)d * n + i];
     }
     r.orig = i;
-    rec[s] = r;
+    rec[inv[i]] = r;
 }
 
 // Symmetric part of each stresslet source tensor q n^T, in sorted order: the stresslet
 // kernel is symmetric in all three indices, so only (q n^T + n q^T)/2 contributes.
 __global__ void k_gather_st(int n, const double* __restrict__ q, const double* __restrict__ nrm,
-                            const int* __restrict__ perm, double* __restrict__ srec)
+                            const int* __restrict__ inv, double* __restrict__ srec)
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const int i = perm[s];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
     const double q0 = q[i], q1 = q[(int64_t)n + i], q2 = q[2 * (int64_t)n + i];
     const double n0 = nrm[i], n1 = nrm[(int64_t)n + i], n2 = nrm[2 * (int64_t)n + i];
-    double* o = srec + 6 * (int64_t)s;
+    double* o = srec + 6 * (int64_t)inv[i];
     o[0] = q0 * n0;
     o[1] = q1 * n1;
     o[2] = q2 * n2;
@@ -434,7 +442,9 @@ hipError_t launch_sort(const Plan& pl, const Work& w, int n, const double* x, co
     const int big_blocks = (int)std::min<int64_t>(512, big_list_cap(n));
     hipLaunchKernelGGL(k_sort_big_cells, dim3(big_blocks), dim3(kBigThreads), 0, s, w.start, w.perm, w.key,
                        w.cell_lists, mid_cap);
-    hipLaunchKernelGGL(k_gather64, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, x, f, w.perm, g,
+    // the key array is free again: it takes the inverse permutation (read by both gathers)
+    hipLaunchKernelGGL(k_invert, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, w.perm, w.key);
+    hipLaunchKernelGGL(k_gather64, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, x, f, w.key, g,
                        (Rec64*)w.rec);
     // P2P work list: waves per tile, then their offsets
     hipLaunchKernelGGL(k_tile_chunks, dim3(blocks_for(ntiles, 256)), dim3(256), 0, s, g, w.start,
@@ -446,7 +456,7 @@ hipError_t launch_gather_st(const Plan& pl, const Work& w, int n, const double* 
                             hipStream_t s)
 {
     (void)pl;
-    hipLaunchKernelGGL(k_gather_st, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, q, nrm, w.perm, w.srec);
+    hipLaunchKernelGGL(k_gather_st, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, q, nrm, w.key, w.srec);
     return hipGetLastError();
 }
 
