@@ -12,6 +12,8 @@
 //           FP64, then the inverse FFT, without leaving LDS;
 //   pass 4  y inverse;
 //   pass 5  z, complex-to-real (the inverse of pass 1).
+// Where a (y, z) plane of one component fits in a workgroup's LDS, passes 1+2 and 4+5 are
+// each one kernel (k_fft_zy, in-place transforms).
 // Each 1D transform is a Stockham radix-4 (plus one radix-2 stage for odd log2 n)
 // autosort FFT held in LDS, one workgroup per batch of adjacent columns (adjacent in
 // memory, so every row of a batch is one contiguous read).  Twiddles come from FP64 host
@@ -186,6 +188,193 @@ __global__ __launch_bounds__(256) void k_fft_z(T* __restrict__ grid, int64_t nce
         for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
             const int c = idx / H, e = idx - c * H;
             if (line0 + c < nlines) data[(int64_t)(line0 + c) * H + e] = z[e * ld + c];
+        }
+    }
+}
+
+// ---- passes 1+2 / 4+5 fused: one (y, z) plane in LDS ----
+//
+// When a whole plane x = const of one component (M2 x M3/2 complex values) fits in the LDS of
+// a workgroup, its z transforms and y transforms are done in one kernel: the plane is read
+// from HBM once and written once per direction (five grid passes become three).  Out-of-place
+// Stockham would need a second plane of LDS, so the transforms here are in place: radix-2
+// Cooley-Tukey stages taken two at a time (each thread holds the four values of two
+// consecutive stages' butterflies), decimation in time from bit-reversed input, or decimation
+// in frequency to bit-reversed output.  The bit reversals cost nothing: they are folded into
+// the global reads and writes, which stay within one plane row (one contiguous run per wave).
+
+__device__ inline int brev_bits(int v, int bits)
+{
+    return (int)(__builtin_bitreverse32((unsigned)v) >> (32 - bits));
+}
+
+// w^s (s = -1: as tabulated, e^{-2 pi i k / n}; s = +1: conjugate)
+template <typename T>
+__device__ inline C2<T> twid(const C2<T>* __restrict__ tw, int k, int sign)
+{
+    C2<T> w = tw[k];
+    if (sign > 0) w.y = -w.y;
+    return w;
+}
+
+// In place, `nt` transforms of length n = 2^m: element e of transform t at a[t * ts + e * es]
+// (nt a power of two; consecutive threads take consecutive transforms, so ts should be the
+// bank-friendly stride).  DIT: bit-reversed input, natural output; DIF: the reverse.
+// tw: the length-n table e^{-2 pi i k / n}.  Ends with a barrier.
+template <typename T, bool DIT>
+__device__ void lds_fft_inplace(C2<T>* a, int n, int m, int nt, int lgnt, int ts, int es, int sign,
+                                const C2<T>* __restrict__ tw)
+{
+    // one radix-2 stage of span q (twiddles W_{2q}^j = tw[j n / (2q)])
+    auto single = [&](int q) {
+        const int nb = n >> 1;
+        for (int idx = threadIdx.x; idx < nt * nb; idx += blockDim.x) {
+            const int t = idx & (nt - 1), bi = idx >> lgnt;
+            const int j = bi & (q - 1), e0 = 2 * (bi - j) + j;
+            C2<T>* p0 = a + t * ts + e0 * es;
+            C2<T>* p1 = p0 + q * es;
+            const C2<T> u = *p0, v = *p1;
+            const C2<T> w = twid(tw, j * (n / (2 * q)), sign);
+            if (DIT) {
+                const C2<T> vw = cmul(v, w);
+                *p0 = cadd(u, vw);
+                *p1 = csub(u, vw);
+            } else {
+                *p0 = cadd(u, v);
+                *p1 = cmul(csub(u, v), w);
+            }
+        }
+        __syncthreads();
+    };
+    // the stages of spans q and 2q (DIT: q first; DIF: 2q first) on the four values at
+    // e0 + {0, q, 2q, 3q}
+    auto pair = [&](int q) {
+        const int nb = n >> 2;
+        for (int idx = threadIdx.x; idx < nt * nb; idx += blockDim.x) {
+            const int t = idx & (nt - 1), bi = idx >> lgnt;
+            const int j = bi & (q - 1), e0 = 4 * (bi - j) + j;
+            C2<T>* p0 = a + t * ts + e0 * es;
+            const int sq = q * es;
+            const C2<T> x0 = p0[0], x1 = p0[sq], x2 = p0[2 * sq], x3 = p0[3 * sq];
+            const C2<T> wa = twid(tw, j * (n / (2 * q)), sign);  // W_{2q}^j
+            const C2<T> wb = twid(tw, j * (n / (4 * q)), sign);  // W_{4q}^j
+            // W_{4q}^{j+q} = W_{4q}^j W_4^1, W_4^1 = -i (forward) or +i (inverse)
+            const C2<T> wc = (sign < 0) ? C2<T>{wb.y, -wb.x} : C2<T>{-wb.y, wb.x};
+            if (DIT) {
+                const C2<T> v1 = cmul(x1, wa), v3 = cmul(x3, wa);
+                const C2<T> t0 = cadd(x0, v1), t1 = csub(x0, v1), t2 = cadd(x2, v3), t3 = csub(x2, v3);
+                const C2<T> u2 = cmul(t2, wb), u3 = cmul(t3, wc);
+                p0[0] = cadd(t0, u2);
+                p0[2 * sq] = csub(t0, u2);
+                p0[sq] = cadd(t1, u3);
+                p0[3 * sq] = csub(t1, u3);
+            } else {
+                const C2<T> t0 = cadd(x0, x2), t2 = cmul(csub(x0, x2), wb);
+                const C2<T> t1 = cadd(x1, x3), t3 = cmul(csub(x1, x3), wc);
+                p0[0] = cadd(t0, t1);
+                p0[sq] = cmul(csub(t0, t1), wa);
+                p0[2 * sq] = cadd(t2, t3);
+                p0[3 * sq] = cmul(csub(t2, t3), wa);
+            }
+        }
+        __syncthreads();
+    };
+    if (DIT) {
+        int q = 1;
+        if (m & 1) {
+            single(1);
+            q = 2;
+        }
+        for (; q < n; q *= 4) pair(q);
+    } else {
+        for (int q = n >> 2; q >= 1; q >>= 2) pair(q);
+        if (m & 1) single(1);
+    }
+}
+
+// sign -1: z (real to half spectrum) then y, forward; sign +1: y then z (half spectrum to real),
+// inverse.  Grid: (M1 planes, components); the plane's LDS rows are padded by one element.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_fft_zy(T* __restrict__ grid, int64_t ncells, int M2, int lgM2, int H,
+                                                 int lgH, int sign, const C2<T>* __restrict__ tw_half,
+                                                 const C2<T>* __restrict__ tw_full, const C2<T>* __restrict__ tw_y)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C2<T>* a = reinterpret_cast<C2<T>*>(smem_raw);
+    const int ld = H + 1;
+    C2<T>* data = reinterpret_cast<C2<T>*>(grid + blockIdx.y * ncells) + (int64_t)blockIdx.x * M2 * H;
+    const int tot = M2 * H;
+    const int half = H >> 1;
+    if (sign < 0) {
+        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+            const int y = idx >> lgH, p = idx & (H - 1);
+            a[y * ld + p] = data[y * H + brev_bits(p, lgH)];
+        }
+        __syncthreads();
+        lds_fft_inplace<T, true>(a, H, lgH, M2, lgM2, ld, 1, -1, tw_half);
+        // half spectrum of the real line from the length-H transform C of its even/odd pairs:
+        // X_k = E_k + e^{-2 pi i k / M3} O_k, E_k = (C_k + conj C_{H-k}) / 2,
+        // O_k = -i (C_k - conj C_{H-k}) / 2; k and H - k are done together (in place)
+        for (int idx = threadIdx.x; idx < M2 * (half + 1); idx += blockDim.x) {
+            const int y = idx & (M2 - 1), k = idx >> lgM2;
+            C2<T>* row = a + y * ld;
+            const int kh = (H - k) & (H - 1);
+            const C2<T> ck = row[k], ch = row[kh];
+            auto unpack = [&](C2<T> c, C2<T> d, int kk) {
+                const C2<T> cm = {d.x, -d.y};
+                const C2<T> E = {(T)0.5 * (c.x + cm.x), (T)0.5 * (c.y + cm.y)};
+                const C2<T> dd = csub(c, cm);
+                const C2<T> O = {(T)0.5 * dd.y, (T)-0.5 * dd.x};
+                return cadd(E, cmul(tw_full[kk], O));
+            };
+            const C2<T> xk = unpack(ck, ch, k);
+            if (kh != k) row[kh] = unpack(ch, ck, kh);
+            row[k] = xk;
+        }
+        __syncthreads();
+        lds_fft_inplace<T, false>(a, M2, lgM2, H, lgH, 1, ld, -1, tw_y);
+        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+            const int p = idx >> lgH, kz = idx & (H - 1);
+            data[brev_bits(p, lgM2) * H + kz] = a[p * ld + kz];
+        }
+    } else {
+        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+            const int p = idx >> lgH, kz = idx & (H - 1);
+            a[p * ld + kz] = data[brev_bits(p, lgM2) * H + kz];
+        }
+        __syncthreads();
+        lds_fft_inplace<T, true>(a, M2, lgM2, H, lgH, 1, ld, +1, tw_y);
+        // the inverse of the unpacking: C_k = E_k + i O_k with E_k = X_k + conj X_{H-k},
+        // O_k = (X_k - conj X_{H-k}) e^{+2 pi i k / M3}; X_0 is real (its imaginary part holds
+        // nothing) and the Nyquist value X_{M3/2} is zero (CNV)
+        for (int idx = threadIdx.x; idx < M2 * (half + 1); idx += blockDim.x) {
+            const int y = idx & (M2 - 1), k = idx >> lgM2;
+            C2<T>* row = a + y * ld;
+            const int kh = (H - k) & (H - 1);
+            const C2<T> xk = row[k], xh = row[kh];
+            auto pack = [&](C2<T> c, C2<T> d, int kk) {
+                C2<T> xm;
+                if (kk == 0) {
+                    c.y = 0;
+                    xm = C2<T>{0, 0};
+                } else {
+                    xm = C2<T>{d.x, -d.y};
+                }
+                const C2<T> E = cadd(c, xm);
+                C2<T> w = tw_full[kk];
+                w.y = -w.y;
+                const C2<T> O = cmul(csub(c, xm), w);
+                return C2<T>{E.x - O.y, E.y + O.x};
+            };
+            const C2<T> ck = pack(xk, xh, k);
+            if (kh != k) row[kh] = pack(xh, xk, kh);
+            row[k] = ck;
+        }
+        __syncthreads();
+        lds_fft_inplace<T, false>(a, H, lgH, M2, lgM2, ld, 1, +1, tw_half);
+        for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+            const int y = idx >> lgH, p = idx & (H - 1);
+            data[y * H + brev_bits(p, lgH)] = a[y * ld + p];
         }
     }
 }
@@ -374,6 +563,15 @@ inline int pow2_floor(int v)
     return p;
 }
 
+// the largest dynamic LDS one workgroup may take on the current device
+int lds_per_block()
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 65536;
+    return v;
+}
+
 template <typename T>
 hipError_t launch_fgc_t(const Plan& pl, const Work& w, hipStream_t s, bool inverse_too, bool cnv, bool st, int nsys)
 {
@@ -388,6 +586,17 @@ hipError_t launch_fgc_t(const Plan& pl, const Work& w, hipStream_t s, bool inver
     const C2<T>* twf = tw + pl.tw_off[3];
     const int budget = (sizeof(T) == 8) ? 1024 : 2048;  // complex elements per buffer
 
+    // passes 1+2 fused when a plane fits in one workgroup's LDS
+    int lgH = 0, lgM2 = 0;
+    while ((1 << lgH) < H) ++lgH;
+    while ((1 << lgM2) < M2) ++lgM2;
+    const size_t shzy = (size_t)M2 * (H + 1) * sizeof(C2<T>);
+    const bool fused = H >= 4 && M2 >= 4 && shzy <= (size_t)lds_per_block();
+    if (fused && shzy > 65536) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_zy<T>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shzy);
+        if (e != hipSuccess) return e;
+    }
     // pass 1: z forward (R2C)
     const int nlines = M1 * M2;
     int ncz = pow2_floor(max(1, budget / H));
@@ -397,15 +606,21 @@ hipError_t launch_fgc_t(const Plan& pl, const Work& w, hipStream_t s, bool inver
     // groups of 3 grid components
     const int ncomp_in = st ? 9 : 3 * nsys;
     dim3 gz((nlines + ncz - 1) / ncz, ncomp_in);
-    hipLaunchKernelGGL((k_fft_z<T>), gz, dim3(256), shz, s, grid, nc, nlines, H, ncz, -1, twh, twf);
     // pass 2: y forward
     int ncy = pow2_floor(max(1, budget / M2));
     if (ncy > H) ncy = H;
     size_t shy = 2 * (size_t)M2 * ncy * sizeof(C2<T>);
     dim3 gy(M1 * (H / ncy), ncomp_in);
-    hipLaunchKernelGGL((k_fft_y<T>), gy, dim3(256), shy, s, grid, nc, M2, H, ncy, -1, tw1);
+    dim3 gzy(M1, ncomp_in);
+    if (fused) {
+        hipLaunchKernelGGL((k_fft_zy<T>), gzy, dim3(1024), shzy, s, grid, nc, M2, lgM2, H, lgH, -1, twh, twf, tw1);
+    } else {
+        hipLaunchKernelGGL((k_fft_z<T>), gz, dim3(256), shz, s, grid, nc, nlines, H, ncz, -1, twh, twf);
+        hipLaunchKernelGGL((k_fft_y<T>), gy, dim3(256), shy, s, grid, nc, M2, H, ncy, -1, tw1);
+    }
     gy.y = 3 * nsys;  // the inverse transforms carry the 3 velocity components
     gz.y = 3 * nsys;
+    gzy.y = 3 * nsys;
     // pass 3: x forward + CNV (+ inverse)
     int ncx = pow2_floor(max(1, budget / (3 * M1)));
     if (ncx > H) ncx = H;
@@ -430,7 +645,9 @@ hipError_t launch_fgc_t(const Plan& pl, const Work& w, hipStream_t s, bool inver
         hipLaunchKernelGGL((k_fft_x_cnv<T>), dim3(M2 * (H / ncx), nsys), dim3(256), shx, s, grid, nc, M1, M2, H,
                            ncx, cnv ? 1 : 0, inverse_too ? 1 : 0, tw0, ca);
     }
-    if (inverse_too) {
+    if (inverse_too && fused) {
+        hipLaunchKernelGGL((k_fft_zy<T>), gzy, dim3(1024), shzy, s, grid, nc, M2, lgM2, H, lgH, +1, twh, twf, tw1);
+    } else if (inverse_too) {
         hipLaunchKernelGGL((k_fft_y<T>), gy, dim3(256), shy, s, grid, nc, M2, H, ncy, +1, tw1);
         hipLaunchKernelGGL((k_fft_z<T>), gz, dim3(256), shz, s, grid, nc, nlines, H, ncz, +1, twh, twf);
     }

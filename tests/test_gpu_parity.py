@@ -57,6 +57,9 @@ CASES = {
     "xlong_P4": ((4.0, 0.5, 0.5), (128, 16, 16), 12.0, 0.2, 4, 3.0),
     # a box 64 times longer in z than across: one tile (8^3 cells) in x and y, 64 along z
     "zlong_P8": ((0.25, 0.25, 16.0), (8, 8, 512), 30.0, 0.1, 8, 4.8),
+    # a (y, z) plane of 128 x 64 complex values: the fused z+y FFT pass with more than 64 KB of
+    # LDS per workgroup (FP64: 133 KB, FP32: 67 KB)
+    "cube128_P8": ((1.0, 1.0, 1.0), (128, 128, 128), 24.0, 0.15, 8, 4.8),
 }
 
 
@@ -87,7 +90,8 @@ def test_p2g_grid_matches_oracle(name, n):
     assert maxrel(g, ref) < 1e-12
 
 
-@pytest.mark.parametrize("name,n", [("cube32_P8", 2000), ("aniso_P12", 1531), ("long_P6", 900), ("xlong_P4", 1200)])
+@pytest.mark.parametrize("name,n", [("cube32_P8", 2000), ("aniso_P12", 1531), ("long_P6", 900), ("xlong_P4", 1200),
+                                    ("cube128_P8", 600)])
 def test_far_grid_matches_oracle(name, n):
     E = _E()
     box, grid, xi, rc, P, m = CASES[name]
@@ -268,7 +272,7 @@ def make_plan32(E, name, n_max, **kw):
     return E.Plan(box, 1e-5, xi=xi, r_c=rc, grid=grid, P=P, window_shape=m, n_max=n_max, precision="fp32", **kw)
 
 
-@pytest.mark.parametrize("name,n", [("cube32_P8", 2000), ("aniso_P12", 1531)])
+@pytest.mark.parametrize("name,n", [("cube32_P8", 2000), ("aniso_P12", 1531), ("cube128_P8", 600)])
 def test_fp32_stages_match_oracle(name, n):
     E = _E()
     box, grid, xi, rc, P, m = CASES[name]
