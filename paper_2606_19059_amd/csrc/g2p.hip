@@ -6,12 +6,16 @@
 //
 // The sum is separable, so for a group of targets whose stencils share one box of grid points
 // it is a matrix product (one grid value serves every target of the group) followed by a short
-// weighted sum per target; the product runs on the FP64 matrix cores (see k_g2p_mfma).  No
-// atomics: each target's result is owned by one lane.  All sums accumulate in FP64 (FP32 bulk
-// included): the far field at a particle contains its own screened self-interaction, about
-// (4 xi / sqrt(pi)) f, which the self term removes; at large xi (fine grids) and for sparse
-// particles that cancellation is large, and FP32 partial sums would set an error floor.
+// weighted sum per target; the product runs on the matrix cores (see k_g2p_mfma).  No
+// atomics: each target's result is owned by one lane.  The far field at a particle contains its
+// own screened self-interaction, about (4 xi / sqrt(pi)) f, which the self term removes; at large
+// xi (fine grids) and for sparse particles that cancellation is large, so FP32 sums over a whole
+// stencil would set an error floor.  With an FP64 grid every sum is FP64; with an FP32 grid (the
+// FP32 bulk mode) only the matrix product sums in FP32, each of its sums covering one z-column of
+// the box over at most U_x U_y points, and the z-weighted sums per target are FP64.
 #include "window.h"
+
+#include <type_traits>
 
 namespace ewald {
 
@@ -92,23 +96,43 @@ __device__ inline void write_target(int s, int orig, int64_t nn, double a0, doub
 // (A is zero off target i's P x P footprint).  The box spans the group's anchors in x and y
 // and the whole tile in z (U_z = B + P - 1, so that the 3 U_z columns of D make a fixed number
 // NB of 16-column blocks per plan).  The contraction runs over the U_x U_y points of the box in
-// steps of 4: v_mfma_f64_16x16x4f64, one instruction per column block, FP64 in and out.  Each
+// steps of 4, one matrix instruction per column block: v_mfma_f64_16x16x4f64 (FP64 in and out),
+// or for FP32 grids and weights v_mfma_f32_16x16x4f32, at twice the FP64 instruction's rate on
+// gfx950 and with half the registers per operand and accumulator.  Each
 // grid value loaded serves all 16 targets of the group, where a per-target gather loads P^3
 // values for every target; the 16 lanes of a column block read 16 consecutive z of one grid
-// line.  Lane layout of the instruction on gfx950: lane l supplies A[l % 16][l / 16] and
-// B[l / 16][l % 16] and receives D[4 r + l / 16][l % 16], r = 0..3.
+// line.  Lane layouts on gfx950: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] (both
+// instructions) and receives D[4 r + l / 16][l % 16] (FP64) or D[4 (l / 16) + r][l % 16] (FP32),
+// r = 0..3.
 typedef double g2p_v4d __attribute__((ext_vector_type(4)));
+typedef float g2p_v4f __attribute__((ext_vector_type(4)));
+__device__ inline g2p_v4d g2p_mfma(double a, double b, g2p_v4d c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+__device__ inline g2p_v4f g2p_mfma(float a, float b, g2p_v4f c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+// operand and accumulator types: FP32 when both the weights and the grid are FP32
+template <typename T, typename TG>
+struct G2PMat {
+    static constexpr bool f32 = std::is_same<T, float>::value && std::is_same<TG, float>::value;
+    typedef typename std::conditional<f32, float, double>::type S;
+    typedef typename std::conditional<f32, g2p_v4f, g2p_v4d>::type V4;
+};
 constexpr int kMG = 16;     // targets per wave (matrix rows)
 constexpr int kMWaves = 4;  // waves per block: one 64-target chunk of a tile
 
 // column blocks of a plan: 3 (B + P - 1) columns
 constexpr int g2p_mfma_blocks(int B, int P) { return (3 * (B + P - 1) + 15) / 16; }
 
-// Up to five column blocks the kernel is bounded to 96 VGPRs (five waves per SIMD instead of
+// Up to five column blocks the FP64 kernel is bounded to 96 VGPRs (five waves per SIMD instead of
 // four): the loads of a step wait on L2 most of the time, and the fifth wave hides more of it
 // (c3 5.73 -> 5.47 ms, H 0.79 -> 0.77 ms, c2 unchanged); six blocks would spill under that bound.
+// The FP32 kernel fits eight waves (64 VGPRs) up to four blocks, and five below P = 16; six
+// otherwise.
 template <typename T, typename TG, int P, int NB>
-__global__ __launch_bounds__(kMWaves * 64) __attribute__((amdgpu_waves_per_eu(NB <= 5 ? 5 : 4))) void k_g2p_mfma(const typename RecView<T>::Rec* __restrict__ rec,
+constexpr int g2p_waves()
+{
+    return G2PMat<T, TG>::f32 ? ((NB <= 4 || (NB == 5 && P < 16)) ? 8 : 6) : (NB <= 5 ? 5 : 4);
+}
+template <typename T, typename TG, int P, int NB>
+__global__ __launch_bounds__(kMWaves * 64) __attribute__((amdgpu_waves_per_eu(g2p_waves<T, TG, P, NB>()))) void k_g2p_mfma(const typename RecView<T>::Rec* __restrict__ rec,
                                                            const int* __restrict__ start,
                                                            const int* __restrict__ chunk_off,
                                                            const TG* __restrict__ grid, Geometry g, WinArgs<T> wa,
@@ -119,6 +143,9 @@ __global__ __launch_bounds__(kMWaves * 64) __attribute__((amdgpu_waves_per_eu(NB
 {
     __shared__ T sw[kMWaves][kMG][3][P];
     __shared__ int anc[kMWaves][kMG][3];
+    typedef typename G2PMat<T, TG>::S TM;
+    // rows of D held by a lane: 4 r + quarter (FP64 instruction) or 4 quarter + r (FP32)
+    constexpr bool kRowsGrouped = G2PMat<T, TG>::f32;
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int nt = g.ntiles * g.nsys;
     const int total = chunk_off[nt];  // 64-target chunks of all tiles of all systems
@@ -187,13 +214,13 @@ __global__ __launch_bounds__(kMWaves * 64) __attribute__((amdgpu_waves_per_eu(NB
         const int jx = xk - dxi, jy = yk - dyi;
         const bool in = (unsigned)jx < (unsigned)P && (unsigned)jy < (unsigned)P;
         const T w = wxi[in ? jx : 0] * wyi[in ? jy : 0];
-        return in ? (double)w : 0.0;
+        return in ? (TM)w : (TM)0;
     };
-    auto load_b = [&](double* b) {
+    auto load_b = [&](TM* b) {
         const unsigned xy =
             (unsigned)((ux + xk) & (M1 - 1)) * plane + (unsigned)((uy + yk) & (M2 - 1)) * (unsigned)M3;
 #pragma unroll
-        for (int cb = 0; cb < NB; ++cb) b[cb] = (double)gs[xy + zc[cb]];
+        for (int cb = 0; cb < NB; ++cb) b[cb] = (TM)gs[xy + zc[cb]];
     };
     auto advance = [&]() {
         yk += 4;
@@ -202,10 +229,12 @@ __global__ __launch_bounds__(kMWaves * 64) __attribute__((amdgpu_waves_per_eu(NB
             ++xk;
         }
     };
-    g2p_v4d acc[NB];
+    typename G2PMat<T, TG>::V4 acc[NB];
 #pragma unroll
-    for (int cb = 0; cb < NB; ++cb) acc[cb] = g2p_v4d{0.0, 0.0, 0.0, 0.0};
-    double a0 = a_of(), b0[NB], a1, b1[NB];
+    for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[cb][r] = (TM)0;
+    TM a0 = a_of(), b0[NB], a1, b1[NB];
     load_b(b0);
 #pragma unroll 1
     for (int st = 0; st < steps; st += 2) {
@@ -214,16 +243,16 @@ __global__ __launch_bounds__(kMWaves * 64) __attribute__((amdgpu_waves_per_eu(NB
         load_b(b1);
         __builtin_amdgcn_sched_barrier(0);  // the loads go out before this step's instructions
 #pragma unroll
-        for (int cb = 0; cb < NB; ++cb) acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0[cb], acc[cb], 0, 0, 0);
+        for (int cb = 0; cb < NB; ++cb) acc[cb] = g2p_mfma(a0, b0[cb], acc[cb]);
         advance();
         a0 = a_of();
         load_b(b0);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int cb = 0; cb < NB; ++cb) acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1[cb], acc[cb], 0, 0, 0);
+        for (int cb = 0; cb < NB; ++cb) acc[cb] = g2p_mfma(a1, b1[cb], acc[cb]);
     }
 
-    // u^F of rows 4 r + kq: weight each column by w_z of its row's target, sum the 16 columns
+    // u^F of this lane's four rows: weight each column by w_z of its row's target, sum the 16 columns
     double p[4][3];
 #pragma unroll
     for (int r = 0; r < 4; ++r) p[r][0] = p[r][1] = p[r][2] = 0.0;
@@ -233,10 +262,10 @@ __global__ __launch_bounds__(kMWaves * 64) __attribute__((amdgpu_waves_per_eu(NB
         const int c = col / Uzt, z = col - c * Uzt;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int q = 4 * r + kq;
+            const int q = kRowsGrouped ? 4 * kq + r : 4 * r + kq;
             const int jz = z + uz - ancq[q][2];
             const bool in = col < ncol && (unsigned)jz < (unsigned)P;
-            const double v = in ? (double)swq[q][2][in ? jz : 0] * acc[cb][r] : 0.0;
+            const double v = in ? (double)swq[q][2][in ? jz : 0] * (double)acc[cb][r] : 0.0;
             p[r][0] += c == 0 ? v : 0.0;
             p[r][1] += c == 1 ? v : 0.0;
             p[r][2] += c == 2 ? v : 0.0;
@@ -252,8 +281,8 @@ __global__ __launch_bounds__(kMWaves * 64) __attribute__((amdgpu_waves_per_eu(NB
         }
     }
     if (i < 4) {
-        // lane i of quarter kq writes row 4 i + kq
-        const int s = sg + 4 * i + kq;
+        // lane i of quarter kq writes its row r = i
+        const int s = sg + (kRowsGrouped ? 4 * kq + i : 4 * i + kq);
         double v0 = p[0][0], v1 = p[0][1], v2 = p[0][2];
 #pragma unroll
         for (int r = 1; r < 4; ++r) {
