@@ -27,6 +27,7 @@ HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 FP32_VECTOR_TFLOPS = 157.3
 FP64_MFMA_PEAK_TFLOPS = 78.6  # dense FP64 matrix (v_mfma_f64_16x16x4f64), the same rate as the vector FMA
+FP32_MFMA_PEAK_TFLOPS = 157.3  # dense FP32 matrix (v_mfma_f32_16x16x4f32: G2P with an FP32 grid)
 # algorithmic cost of one (target, source) pair inside r_c (documented in the design notes):
 # 39 add/mul (FMA = 2) of the G^N f formula + 7 per special function (rsqrt, exp, erfc).
 # Counted per ordered pair, whatever the kernel executes (the symmetric kernel evaluates the
@@ -51,7 +52,8 @@ def stage_roofline(stages, n, ncell, P, real, pairs, alu_peak_tflops):
 
     sort: bytes N (24 + 48 + 64 + 16) + 12 per cell; P2P: 60 flop per pair in r_c; P2G and G2P: 7 flop per
     (particle, stencil point), bytes 64 per record + one pass over the 3-component grid (+ 72 per particle
-    written/gathered by G2P; G2P runs on the FP64 matrix cores, priced against their peak);
+    written/gathered by G2P; G2P runs on the FP64 matrix cores, or the FP32 ones with an FP32 grid,
+    priced against that peak);
     FFT+CNV+IFFT: five passes, each reading and writing the 3-component grid.
     """
     out = {}
@@ -67,8 +69,8 @@ def stage_roofline(stages, n, ncell, P, real, pairs, alu_peak_tflops):
         e["bound"] = bound
         if bound == "alu":
             e["frac"] = e["TFLOPs"] / alu_peak_tflops
-        elif bound == "mfma":  # FP64 matrix instructions in every mode
-            e["frac"] = e["TFLOPs"] / FP64_MFMA_PEAK_TFLOPS
+        elif bound == "mfma":  # FP32 matrix instructions with an FP32 grid, else FP64
+            e["frac"] = e["TFLOPs"] / (FP32_MFMA_PEAK_TFLOPS if real == 4 else FP64_MFMA_PEAK_TFLOPS)
         else:
             e["frac"] = e["GBs"] / HBM_PEAK_GBS
         out[name] = e
