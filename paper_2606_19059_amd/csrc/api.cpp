@@ -200,10 +200,10 @@ struct CostModel {
     double fft_cell, fft0;
     double sort, sort_cell, sort0;
 };
-constexpr CostModel kCost64 = {5.217, 0.053, 0.108, 0.169, 0.072, 43.585, 2.914, 0.0039, 0.0, 0.076, 0.030,
-                               0.216, 0.008, 0.044};
-constexpr CostModel kCost32 = {4.423, 0.045, 0.146, 0.171, 0.059, 53.008, 2.957, 0.0, 0.0041, 0.048, 0.042,
-                               0.223, 0.006, 0.044};
+constexpr CostModel kCost64 = {5.217, 0.053, 0.108, 0.169, 0.072, 46.477, 2.738, 0.0037, 0.0, 0.066, 0.017,
+                               0.177, 0.010, 0.052};
+constexpr CostModel kCost32 = {4.423, 0.045, 0.146, 0.171, 0.059, 37.097, 2.584, 0.0002, 0.0016, 0.041, 0.021,
+                               0.174, 0.010, 0.056};
 constexpr double kWaveSlots = 2048.0;  // concurrent P2P waves at which the chip is full
 
 int p2g_blocks(const int M[3], int P)
@@ -244,8 +244,9 @@ double model_ms(int mode, bool grid64, double n, const double box[3], const int 
     st[1] = c.pair * pairs * 1e-9 / std::min(1.0, waves / kWaveSlots) + c.p2p0;
     st[2] = c.p2g * np3 * 1e-9 / std::min(1.0, p2g_blocks(M, P) / 1024.0) + c.p2g_cell * cells * 1e-6 + c.p2g0;
     st[3] = cf.fft_cell * cells * 1e-6 + cf.fft0;
-    st[4] = (c.g2p * groups * std::ceil(U * U / 4.0) * NB * 1e-9 + c.g2p_group * groups * 1e-6) / g2p_occ +
-            c.g2p_cell * cells * 1e-6 + c.g2p0;
+    // G2P's matrix instruction follows the grid's precision (FP32 only for an FP32 grid)
+    st[4] = (cf.g2p * groups * std::ceil(U * U / 4.0) * NB * 1e-9 + cf.g2p_group * groups * 1e-6) / g2p_occ +
+            cf.g2p_cell * cells * 1e-6 + cf.g2p0;
     double t = 0;
     for (int k = 0; k < 5; ++k) {
         if (stage) stage[k] = st[k];
