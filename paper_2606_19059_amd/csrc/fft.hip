@@ -217,21 +217,23 @@ __device__ inline C2<T> twid(const C2<T>* __restrict__ tw, int k, int sign)
     return w;
 }
 
-// In place, `nt` transforms of length n = 2^m: element e of transform t at a[t * ts + e * es]
-// (nt a power of two; consecutive threads take consecutive transforms, so ts should be the
-// bank-friendly stride).  DIT: bit-reversed input, natural output; DIF: the reverse.
-// tw: the length-n table e^{-2 pi i k / n}.  Ends with a barrier.
+// In place, `nt` transforms of length n = 2^m for each of `ncomp` components: element e of
+// transform t of component k at a[k * cs + t * ts + e * es] (nt a power of two; consecutive
+// threads take consecutive transforms, so ts should be the bank-friendly stride).  DIT:
+// bit-reversed input, natural output; DIF: the reverse.  tw: the length-n table
+// e^{-2 pi i k / n}.  Ends with a barrier.
 template <typename T, bool DIT>
 __device__ void lds_fft_inplace(C2<T>* a, int n, int m, int nt, int lgnt, int ts, int es, int sign,
-                                const C2<T>* __restrict__ tw)
+                                const C2<T>* __restrict__ tw, int ncomp = 1, int cs = 0)
 {
     // one radix-2 stage of span q (twiddles W_{2q}^j = tw[j n / (2q)])
     auto single = [&](int q) {
-        const int nb = n >> 1;
-        for (int idx = threadIdx.x; idx < nt * nb; idx += blockDim.x) {
-            const int t = idx & (nt - 1), bi = idx >> lgnt;
+        const int nb = n >> 1, lgnb = m - 1;
+        for (int idx = threadIdx.x; idx < nt * nb * ncomp; idx += blockDim.x) {
+            const int t = idx & (nt - 1), rest = idx >> lgnt;
+            const int bi = rest & (nb - 1), k = rest >> lgnb;
             const int j = bi & (q - 1), e0 = 2 * (bi - j) + j;
-            C2<T>* p0 = a + t * ts + e0 * es;
+            C2<T>* p0 = a + k * cs + t * ts + e0 * es;
             C2<T>* p1 = p0 + q * es;
             const C2<T> u = *p0, v = *p1;
             const C2<T> w = twid(tw, j * (n / (2 * q)), sign);
@@ -249,11 +251,12 @@ __device__ void lds_fft_inplace(C2<T>* a, int n, int m, int nt, int lgnt, int ts
     // the stages of spans q and 2q (DIT: q first; DIF: 2q first) on the four values at
     // e0 + {0, q, 2q, 3q}
     auto pair = [&](int q) {
-        const int nb = n >> 2;
-        for (int idx = threadIdx.x; idx < nt * nb; idx += blockDim.x) {
-            const int t = idx & (nt - 1), bi = idx >> lgnt;
+        const int nb = n >> 2, lgnb = m - 2;
+        for (int idx = threadIdx.x; idx < nt * nb * ncomp; idx += blockDim.x) {
+            const int t = idx & (nt - 1), rest = idx >> lgnt;
+            const int bi = rest & (nb - 1), k = rest >> lgnb;
             const int j = bi & (q - 1), e0 = 4 * (bi - j) + j;
-            C2<T>* p0 = a + t * ts + e0 * es;
+            C2<T>* p0 = a + k * cs + t * ts + e0 * es;
             const int sq = q * es;
             const C2<T> x0 = p0[0], x1 = p0[sq], x2 = p0[2 * sq], x3 = p0[3 * sq];
             const C2<T> wa = twid(tw, j * (n / (2 * q)), sign);  // W_{2q}^j
@@ -420,6 +423,26 @@ struct CnvArgs {
     const double* E2;
 };
 
+// CNV at one wavenumber k = (k0, k1, k2) (index kx, kz; e1 = E1[ky]) of the three components
+// r[idx], r[per + idx], r[2 per + idx]: the scaling of eq. (sca) with Ghat^F of eq. (GFk), FP64
+template <typename T>
+__device__ inline void cnv_point(C2<T>* r, int per, int idx, int kx, int kz, double k0, double k1, double k2,
+                                 double e1, const CnvArgs& ca)
+{
+    const double K2 = k0 * k0 + k1 * k1 + k2 * k2;
+    double A = 0.0;
+    if (K2 > 0.0) A = ca.E0[kx] * e1 * ca.E2[kz] * ca.eightpi * (1.0 + K2 * ca.inv4xi2) / (K2 * K2);
+    C2<T>* p0 = &r[idx];
+    C2<T>* p1 = &r[per + idx];
+    C2<T>* p2 = &r[2 * per + idx];
+    const double q0r = p0->x, q0i = p0->y, q1r = p1->x, q1i = p1->y, q2r = p2->x, q2i = p2->y;
+    const double dr = k0 * q0r + k1 * q1r + k2 * q2r;
+    const double di = k0 * q0i + k1 * q1i + k2 * q2i;
+    *p0 = C2<T>{(T)(A * (K2 * q0r - k0 * dr)), (T)(A * (K2 * q0i - k0 * di))};
+    *p1 = C2<T>{(T)(A * (K2 * q1r - k1 * dr)), (T)(A * (K2 * q1i - k1 * di))};
+    *p2 = C2<T>{(T)(A * (K2 * q2r - k2 * dr)), (T)(A * (K2 * q2i - k2 * di))};
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_fft_x_cnv(T* __restrict__ grid, int64_t ncells, int M1, int M2,
                                                    int H, int ncols, int do_cnv, int do_inv,
@@ -455,19 +478,7 @@ __global__ __launch_bounds__(256) void k_fft_x_cnv(T* __restrict__ grid, int64_t
             const int kz = kz0 + c;
             const int kxs = (kx < M1 / 2) ? kx : kx - M1;
             const double k0 = ca.twopi_over_L[0] * kxs;
-            const double k2 = ca.twopi_over_L[2] * kz;
-            const double K2 = k0 * k0 + k1 * k1 + k2 * k2;
-            double A = 0.0;
-            if (K2 > 0.0) A = ca.E0[kx] * e1 * ca.E2[kz] * ca.eightpi * (1.0 + K2 * ca.inv4xi2) / (K2 * K2);
-            C2<T>* p0 = &r[idx];
-            C2<T>* p1 = &r[per + idx];
-            C2<T>* p2 = &r[2 * per + idx];
-            const double q0r = p0->x, q0i = p0->y, q1r = p1->x, q1i = p1->y, q2r = p2->x, q2i = p2->y;
-            const double dr = k0 * q0r + k1 * q1r + k2 * q2r;
-            const double di = k0 * q0i + k1 * q1i + k2 * q2i;
-            *p0 = C2<T>{(T)(A * (K2 * q0r - k0 * dr)), (T)(A * (K2 * q0i - k0 * di))};
-            *p1 = C2<T>{(T)(A * (K2 * q1r - k1 * dr)), (T)(A * (K2 * q1i - k1 * di))};
-            *p2 = C2<T>{(T)(A * (K2 * q2r - k2 * dr)), (T)(A * (K2 * q2i - k2 * di))};
+            cnv_point(r, per, idx, kx, kz, k0, k1, ca.twopi_over_L[2] * kz, e1, ca);
         }
         __syncthreads();
     }
@@ -489,6 +500,53 @@ __global__ __launch_bounds__(256) void k_fft_x_cnv(T* __restrict__ grid, int64_t
 // (k^2 (delta_bc k_a + delta_ab k_c + delta_ac k_b) - 2 k_a k_b k_c), contracted with the
 // symmetric S), A = 8 pi / k^4 (1 + k^2/(4 xi^2)) e^{-k^2/(4 xi^2)} / what^2 with the DFT and
 // h^3 scales folded in; then the inverse x transform of the 3 results.
+// The same pass (forward x FFT, CNV, inverse x FFT of the three components) with one LDS buffer:
+// in-place stages (see lds_fft_inplace), forward by decimation in frequency, which leaves LDS row p
+// holding kx = the bit reversal of p, CNV on that order, inverse by decimation in time, which
+// takes it back to natural order.  Twice the columns per block of the two-buffer kernel in the
+// same LDS.  lgM1, lgnc: log2 of M1 and of ncols.
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_x_cnv_ip(T* __restrict__ grid, int64_t ncells, int M1, int lgM1,
+                                                      int M2, int H, int ncols, int lgnc,
+                                                      const C2<T>* __restrict__ tw, CnvArgs ca)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int per = M1 * ncols;  // elements per component (power of two)
+    C2<T>* a = reinterpret_cast<C2<T>*>(smem_raw);
+    grid += (int64_t)blockIdx.y * 3 * ncells;  // system blockIdx.y of a batch
+    const int tiles_per_y = H / ncols;
+    const int bx = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int ky = bx / tiles_per_y;
+    const int kz0 = (bx - ky * tiles_per_y) * ncols;
+    const int64_t rowstride = (int64_t)M2 * H;  // complex elements between consecutive x
+    const int tot = 3 * per;
+    for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+        const int comp = idx / per, rem = idx - comp * per;
+        const int e = rem >> lgnc, c = rem & (ncols - 1);
+        const C2<T>* data = reinterpret_cast<const C2<T>*>(grid + comp * ncells);
+        a[idx] = data[(int64_t)e * rowstride + (int64_t)ky * H + kz0 + c];
+    }
+    __syncthreads();
+    lds_fft_inplace<T, false>(a, M1, lgM1, ncols, lgnc, 1, ncols, -1, tw, 3, per);
+    const int kys = (ky < M2 / 2) ? ky : ky - M2;
+    const double k1 = ca.twopi_over_L[1] * kys;
+    const double e1 = ca.E1[ky];
+    for (int idx = threadIdx.x; idx < per; idx += blockDim.x) {
+        const int kx = brev_bits(idx >> lgnc, lgM1), c = idx & (ncols - 1);
+        const int kz = kz0 + c;
+        const int kxs = (kx < M1 / 2) ? kx : kx - M1;
+        cnv_point(a, per, idx, kx, kz, ca.twopi_over_L[0] * kxs, k1, ca.twopi_over_L[2] * kz, e1, ca);
+    }
+    __syncthreads();
+    lds_fft_inplace<T, true>(a, M1, lgM1, ncols, lgnc, 1, ncols, +1, tw, 3, per);
+    for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+        const int comp = idx / per, rem = idx - comp * per;
+        const int e = rem >> lgnc, c = rem & (ncols - 1);
+        C2<T>* data = reinterpret_cast<C2<T>*>(grid + comp * ncells);
+        data[(int64_t)e * rowstride + (int64_t)ky * H + kz0 + c] = a[idx];
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_cnv_st_x(T* __restrict__ grid, int64_t ncells, int M1, int M2, int H,
                                                   int ncols, const C2<T>* __restrict__ tw, CnvArgs ca)
@@ -641,6 +699,16 @@ hipError_t launch_fgc_t(const Plan& pl, const Work& w, hipStream_t s, bool inver
         if (cnv && inverse_too)
             hipLaunchKernelGGL((k_cnv_st_x<T>), dim3(M2 * (H / ncx)), dim3(256), shx, s, grid, nc, M1, M2, H, ncx,
                                tw0, ca);
+    } else if (cnv && inverse_too && M1 >= 4) {
+        // one LDS buffer: twice the columns per block
+        int lgM1 = 0, lgnc = 0;
+        while ((1 << lgM1) < M1) ++lgM1;
+        int nci = pow2_floor(max(1, 2 * budget / (3 * M1)));
+        if (nci > H) nci = H;
+        while ((1 << lgnc) < nci) ++lgnc;
+        const size_t shi = (size_t)3 * M1 * nci * sizeof(C2<T>);
+        hipLaunchKernelGGL((k_fft_x_cnv_ip<T>), dim3(M2 * (H / nci), nsys), dim3(256), shi, s, grid, nc, M1, lgM1,
+                           M2, H, nci, lgnc, tw0, ca);
     } else {
         hipLaunchKernelGGL((k_fft_x_cnv<T>), dim3(M2 * (H / ncx), nsys), dim3(256), shx, s, grid, nc, M1, M2, H,
                            ncx, cnv ? 1 : 0, inverse_too ? 1 : 0, tw0, ca);
